@@ -1,0 +1,192 @@
+/*
+ * usp.h -- C ABI of the MI355X (gfx950) universal-split-preconditioner solver.
+ *
+ * Method: Vettenburg & Vellekoop, "A universal matrix-free split preconditioner
+ * for the fixed-point iterative solution of non-symmetric linear systems"
+ * (arXiv 2207.14222).  A canonical system A x = y with A = L + V, ||V|| < 1,
+ * A accretive (Sec. 2, Theorem 1) is solved by the preconditioned fixed-point
+ * iteration with the forward problem eliminated (Sec. 2.1, Algorithm 1):
+ *
+ *     Delta = B [ (L + I)^-1 (B x + y) - x ],   x <- x + alpha Delta,   B = I - V,
+ *
+ * with (L + I)^-1 applied through the analytic Fourier symbol of L
+ * (Eq. laplacian_inverse): F^-1 diag(1/(l(p) + 1)) F on a periodic grid.
+ *
+ * Conventions (all entry points):
+ *   - Return value: 0 = OK / converged; > 0 = solver outcome (USP_MAXIT,
+ *     USP_STAGNATED, USP_DIVERGED: the paper's "m", "s", "d" of Table 1);
+ *     < 0 = error (USP_ERR_*).  The message of the last error on the calling
+ *     thread is returned by usp_last_error().  No C++ exception crosses the ABI.
+ *   - Device buffers ("_dev") are plain device pointers owned by the caller,
+ *     C-ordered (last axis contiguous), complex interleaved (re, im), 8-byte
+ *     aligned at least; dtype USP_C64 = float2 elements, USP_C128 = double2.
+ *   - The library never allocates device memory: every scratch array lives in a
+ *     caller-provided workspace of usp_workspace_bytes() bytes.
+ *   - All device work is issued on the stream given to usp_prepare_operator
+ *     (a hipStream_t passed as void*; NULL = default stream).  Solves are
+ *     synchronous with respect to their host outputs.  An operator handle is
+ *     not thread-safe; use one handle per stream.
+ *   - Grid sizes: ndim 1: n in {8, ..., 1024} (power of two, single-workgroup
+ *     solver); ndim 2 or 3: every axis in {8, ..., 1024} (power of two).
+ */
+#ifndef USP_H
+#define USP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status and error codes */
+#define USP_OK 0
+#define USP_MAXIT 1
+#define USP_STAGNATED 2
+#define USP_DIVERGED 3
+#define USP_ERR_INVALID (-1)
+#define USP_ERR_UNSUPPORTED_SHAPE (-2)
+#define USP_ERR_NOT_CONTRACTIVE (-3)
+#define USP_ERR_HIP (-4)
+#define USP_ERR_NAN (-5)
+#define USP_ERR_WORKSPACE (-6)
+
+/* element types */
+#define USP_C64 0
+#define USP_C128 1
+
+/* prepare flags */
+#define USP_FLAG_REFINE 1 /* complex64 inner iterations, FP64 outer refinement (needs USP_C128 buffers) */
+
+/* bias kinds for usp_smallest_circle */
+#define USP_BIAS_COMPLEX 0
+#define USP_BIAS_REAL 1
+
+/*
+ * Fourier symbol of L (Sec. 2.2 canonical form; Sec. 3.1 Helmholtz, 3.2
+ * diffusion, 3.3 pantograph):
+ *     l(p) = s * (a0 + a2 |p|^2 + a1 * i * p_0)        (a1 term: ndim == 1 only)
+ * on the FFT grid p_k = 2 pi fftfreq(n_k, h_k).  When nyquist_zero is set, the
+ * first-derivative term i p is zero at the Nyquist index (keeps d/dt
+ * skew-Hermitian).  Complex coefficients are (re, im) pairs.
+ *   Helmholtz:  s = 1/c, a0 = kbar^2, a2 = -1            (c = i R / 0.95)
+ *   diffusion:  s = 1/c, a0 = mubar - i omega/v, a2 = D  (c = R / 0.95)
+ *   pantograph: s = 1/c, a0 = abar, a1 = 1               (c real)
+ */
+typedef struct {
+  int ndim;           /* 1, 2 or 3 */
+  int shape[3];       /* C order; shape[ndim-1] is the contiguous axis */
+  double spacing[3];  /* grid spacing h per axis */
+  double s[2];
+  double a0[2];
+  double a1[2];
+  double a2[2];
+  int nyquist_zero;
+} usp_symbol;
+
+/* Pantograph dilation gather (Sec. 3.3, ndim == 1 only): V adds
+ *     (G x)_j = g0_j x[idx_j] + g1_j x[min(idx_j + 1, n - 1)].
+ * idx_dev: int32[n]; g0_dev, g1_dev: complex[n] of the operator's dtype.
+ * Device arrays, caller-owned, must outlive the handle. */
+typedef struct {
+  const int32_t* idx_dev;
+  const void* g0_dev;
+  const void* g1_dev;
+} usp_gather;
+
+typedef struct usp_op_s* usp_op;
+
+/* Workspace size for an operator.  dtype: USP_C64 or USP_C128; flags: 0 or
+ * USP_FLAG_REFINE (requires USP_C128).  Errors: INVALID, UNSUPPORTED_SHAPE. */
+int usp_workspace_bytes(const usp_symbol* L, int dtype, int flags, size_t* bytes);
+
+/* Prepare an operator handle (Sec. 2.1: the iteration needs B = I - V and the
+ * symbol of L).
+ *   B_dev      diagonal of B = 1 - v (N elements of dtype), caller-owned, must
+ *              outlive the handle.  Validated: max |1 - B| must be < 1
+ *              (||V|| < 1, Theorem 1), else USP_ERR_NOT_CONTRACTIVE (diagonal
+ *              part only when a gather is present).
+ *   gather     NULL, or the pantograph gather (ndim == 1).
+ *   workspace  device buffer of usp_workspace_bytes() bytes (>= 256-B aligned);
+ *              owned by the caller, used exclusively by this handle.
+ *   stream     hipStream_t or NULL.
+ * In refined mode B_dev is complex128; the library writes a complex64 copy of
+ * B into the workspace for the inner iterations. */
+int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* B_dev, const usp_gather* gather,
+                         void* workspace_dev, size_t workspace_bytes, void* stream, usp_op* out);
+
+/* Algorithm 1 (Sec. 2.1) until ||y - A x|| / ||y|| < tol.
+ *   y_dev, x_dev   right-hand side and solution (dtype of the handle; complex128
+ *                  in refined mode).  x_dev is read as the initial guess when
+ *                  x_is_guess != 0, otherwise the iteration starts from x = 0.
+ *                  On return x_dev holds the last iterate.
+ *   alpha          step size (> 0; (0, 1] is always contractive, Corollary 1).
+ *   check_every    true residual evaluated (in FP64) every check_every
+ *                  iterations; in refined mode this is the refinement interval
+ *                  k (residual recomputed and accumulated in FP64 every k steps).
+ *   iters_out      iterations performed.
+ *   hist_pre       host array, may be NULL: ||Delta_i||^2 for i < hist_pre_cap.
+ *   hist_true      host array, may be NULL: pairs (iteration, ||y - A x||/||y||)
+ *                  for each check, up to hist_true_cap pairs; n_true_out gets
+ *                  the number of checks performed.
+ * Returns USP_OK (converged), USP_MAXIT, USP_STAGNATED (no 1% improvement of
+ * the true residual over 8 checks), USP_DIVERGED, or an error. */
+int usp_solve(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double alpha, double tol, int maxit,
+              int check_every, int* iters_out, double* hist_pre, int hist_pre_cap, double* hist_true,
+              int hist_true_cap, int* n_true_out);
+
+/* Test hook: exactly K iterations of Algorithm 1 from x_dev (in/out; x_is_guess
+ * as in usp_solve).  hist_pre as in usp_solve.  Not available in refined mode. */
+int usp_iterate(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double alpha, int K, double* hist_pre,
+                int hist_pre_cap);
+
+/* True relative residual ||y - A x|| / ||y|| evaluated in FP64 (A = L + V,
+ * canonical form, Sec. 2.2).  rnorm_out / ynorm_out may be NULL. */
+int usp_residual(usp_op op, const void* y_dev, const void* x_dev, double* rel_out, double* rnorm_out,
+                 double* ynorm_out);
+
+/* Destroy a handle (frees host memory only). */
+int usp_destroy(usp_op op);
+
+/* Message of the last error on this thread ("" if none). */
+const char* usp_last_error(void);
+
+/* ---- canonicalisation helpers (Sec. 2.2, 3.1, 3.2) ---------------------- */
+
+/* Centre and radius of the smallest disc containing n complex points (host
+ * array of 2n doubles).  kind USP_BIAS_COMPLEX: unrestricted centre (the
+ * smallest-circle problem of Sec. 3.1); USP_BIAS_REAL: centre restricted to the
+ * real axis (real bias, Sec. 4.1).  centre_out: 2 doubles. */
+int usp_smallest_circle(const double* pts_host, size_t n, int kind, double* centre_out, double* radius_out);
+
+/* B and y of a canonical problem with diagonal V (Sec. 2.2):
+ *     B = 1 - (q - bias)/c,   y = src_scale * S / c
+ * q_dev, S_dev: complex128[n] device arrays (k^2 or mu_a, and the raw source);
+ * B_dev, y_dev: outputs of dtype (either may be NULL).  Helmholtz: q = k^2,
+ * src_scale = -1; diffusion: q = mu_a (+0i), src_scale = +1.  Runs on `stream`. */
+int usp_canonical_fields(const void* q_dev, const void* S_dev, size_t n, const double* bias, const double* c,
+                         double src_scale, int dtype, void* B_dev, void* y_dev, void* stream);
+
+/* Helmholtz canonical form (Sec. 3.1, Eq. laplacian_inverse): raw problem
+ * (laplacian + k^2) psi = -S.  Computes kbar^2 (smallest-circle centre of the n
+ * values k2_host, complex or real-axis per bias_kind) and c = i R / vnorm, or
+ * takes both from `given` = {kbar^2 re, im, c re, im} (required for a
+ * homogeneous medium, R = 0).  grid: ndim/shape/spacing to copy; sym_out gets
+ * s = 1/c, a0 = kbar^2, a2 = -1.  c_out, bias_out: 2 doubles each.  Host only.
+ * Then usp_canonical_fields(k^2, S, bias, c, -1, ...) gives B and y on device. */
+int usp_canonical_helmholtz(const double* k2_host, size_t n, int bias_kind, const double* given, double vnorm,
+                            const usp_symbol* grid, usp_symbol* sym_out, double* c_out, double* bias_out);
+
+/* Constant-D frequency-domain diffusion (Sec. 3.2, scalar form):
+ * A0 = -D laplacian + mu_a - i omega/v.  mubar = midrange of mu_a (smallest
+ * circle of a real set), c = R / vnorm.  sym_out: s = 1/c,
+ * a0 = mubar - i omega/v, a2 = D.  Then usp_canonical_fields(mu_a, S, mubar, c,
+ * +1, ...).  Host only. */
+int usp_canonical_diffusion(const double* mu_host, size_t n, double D, double omega_over_v, double vnorm,
+                            const usp_symbol* grid, usp_symbol* sym_out, double* c_out, double* bias_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* USP_H */

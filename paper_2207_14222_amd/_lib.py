@@ -1,0 +1,88 @@
+"""ctypes binding of ``libusp.so`` (argument marshalling only).
+
+The functions here have the same names and arguments as the C ABI declared in
+``include/usp.h``.  Loading fails loudly when the library has not been built:
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libusp.so")
+
+USP_OK, USP_MAXIT, USP_STAGNATED, USP_DIVERGED = 0, 1, 2, 3
+USP_ERR_INVALID, USP_ERR_UNSUPPORTED_SHAPE, USP_ERR_NOT_CONTRACTIVE = -1, -2, -3
+USP_ERR_HIP, USP_ERR_NAN, USP_ERR_WORKSPACE = -4, -5, -6
+USP_C64, USP_C128 = 0, 1
+USP_FLAG_REFINE = 1
+USP_BIAS_COMPLEX, USP_BIAS_REAL = 0, 1
+
+STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "invalid",
+                -2: "unsupported_shape", -3: "not_contractive", -4: "hip_error", -5: "nan", -6: "workspace"}
+
+EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iterate", "usp_residual",
+           "usp_destroy", "usp_last_error", "usp_smallest_circle", "usp_canonical_fields",
+           "usp_canonical_helmholtz", "usp_canonical_diffusion"]
+
+
+class usp_symbol(ct.Structure):
+    _fields_ = [("ndim", ct.c_int), ("shape", ct.c_int * 3), ("spacing", ct.c_double * 3),
+                ("s", ct.c_double * 2), ("a0", ct.c_double * 2), ("a1", ct.c_double * 2),
+                ("a2", ct.c_double * 2), ("nyquist_zero", ct.c_int)]
+
+
+class usp_gather(ct.Structure):
+    _fields_ = [("idx_dev", ct.c_void_p), ("g0_dev", ct.c_void_p), ("g1_dev", ct.c_void_p)]
+
+
+class UspError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libusp.so (raises if it is missing: the HIP library is mandatory)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built; run `python -m paper_2207_14222_amd.build`")
+    L = ct.CDLL(LIB_PATH)
+    P, D, I, Z = ct.c_void_p, ct.c_double, ct.c_int, ct.c_size_t
+    DP, IP = ct.POINTER(ct.c_double), ct.POINTER(ct.c_int)
+    L.usp_workspace_bytes.argtypes = [ct.POINTER(usp_symbol), I, I, ct.POINTER(Z)]
+    L.usp_prepare_operator.argtypes = [ct.POINTER(usp_symbol), I, I, P, ct.POINTER(usp_gather), P, Z, P,
+                                       ct.POINTER(P)]
+    L.usp_solve.argtypes = [P, P, P, I, D, D, I, I, IP, DP, I, DP, I, IP]
+    L.usp_iterate.argtypes = [P, P, P, I, D, I, DP, I]
+    L.usp_residual.argtypes = [P, P, P, DP, DP, DP]
+    L.usp_destroy.argtypes = [P]
+    L.usp_last_error.argtypes = []
+    L.usp_last_error.restype = ct.c_char_p
+    L.usp_smallest_circle.argtypes = [DP, Z, I, DP, DP]
+    L.usp_canonical_fields.argtypes = [P, P, Z, DP, DP, D, I, P, P, P]
+    SP = ct.POINTER(usp_symbol)
+    L.usp_canonical_helmholtz.argtypes = [DP, Z, I, DP, D, SP, SP, DP, DP]
+    L.usp_canonical_diffusion.argtypes = [DP, Z, D, D, D, SP, SP, DP, DP]
+    for name in EXPORTS:
+        if name != "usp_last_error":
+            getattr(L, name).restype = ct.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().usp_last_error().decode()
+
+
+def check(rc: int) -> int:
+    """Raise UspError for negative return codes; pass solver outcomes through."""
+    if rc < 0:
+        raise UspError(rc, last_error())
+    return rc

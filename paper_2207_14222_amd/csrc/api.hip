@@ -1,0 +1,762 @@
+// C ABI of the solver: operator handles, workspace layout, pass scheduling,
+// the fixed-point solve loop (Algorithm 1, Sec. 2.1), FP64 residual checks and
+// outer refinement, and host canonicalisation helpers (Sec. 2.2, 3.1).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/usp.h"
+#include "passes.hpp"
+#include "solve1d.hpp"
+#include "util.hpp"
+
+using namespace usp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(USP_ERR_HIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCHCHK(what)                                                                \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess) return fail(USP_ERR_HIP, std::string(what ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int kHist = 1 << 16;   // device ring of ||Delta||^2 values
+constexpr int kMinN = 8, kMaxN = 1024;
+
+bool pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
+int ilog2(long n) {
+  int l = 0;
+  while ((1L << l) < n) ++l;
+  return l;
+}
+
+template <class F>
+bool with_n(int n, F&& f) {
+  switch (n) {
+    case 8: f(std::integral_constant<int, 8>{}); return true;
+    case 16: f(std::integral_constant<int, 16>{}); return true;
+    case 32: f(std::integral_constant<int, 32>{}); return true;
+    case 64: f(std::integral_constant<int, 64>{}); return true;
+    case 128: f(std::integral_constant<int, 128>{}); return true;
+    case 256: f(std::integral_constant<int, 256>{}); return true;
+    case 512: f(std::integral_constant<int, 512>{}); return true;
+    case 1024: f(std::integral_constant<int, 1024>{}); return true;
+    default: return false;
+  }
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t t = 0, S = 0, B32 = 0, r32 = 0, d32 = 0;
+  size_t partials = 0, counters = 0, slots = 0, hist = 0, scal = 0, hist_true = 0, info = 0;
+  size_t twf[11] = {0}, twd[11] = {0};
+  size_t q0 = 0, q1 = 0, q2 = 0, qzero = 0;
+  size_t total = 0;
+  long nblk = 0;
+};
+
+struct Dims {
+  int ndim, n0, n1, n2;
+  long N;
+};
+
+int get_dims(const usp_symbol* L, Dims* d) {
+  if (!L) return fail(USP_ERR_INVALID, "symbol is NULL");
+  if (L->ndim < 1 || L->ndim > 3) return fail(USP_ERR_INVALID, "ndim must be 1, 2 or 3");
+  for (int a = 0; a < L->ndim; ++a)
+    if (!pow2_in_range(L->shape[a]))
+      return fail(USP_ERR_UNSUPPORTED_SHAPE, "every axis length must be a power of two in [8, 1024]");
+  d->ndim = L->ndim;
+  if (L->ndim == 1) {
+    d->n0 = 1; d->n1 = 1; d->n2 = L->shape[0];
+  } else if (L->ndim == 2) {
+    d->n0 = L->shape[0]; d->n1 = 1; d->n2 = L->shape[1];
+  } else {
+    d->n0 = L->shape[0]; d->n1 = L->shape[1]; d->n2 = L->shape[2];
+  }
+  d->N = (long)d->n0 * d->n1 * d->n2;
+  return 0;
+}
+
+int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, Dims* dims) {
+  int rc = get_dims(L, dims);
+  if (rc) return rc;
+  if (dtype != USP_C64 && dtype != USP_C128) return fail(USP_ERR_INVALID, "dtype must be USP_C64 or USP_C128");
+  const bool refine = (flags & USP_FLAG_REFINE) != 0;
+  if (refine && dtype != USP_C128) return fail(USP_ERR_INVALID, "refined mode needs USP_C128 buffers");
+  if (refine && dims->ndim == 1) return fail(USP_ERR_INVALID, "refined mode is for 2-D / 3-D grids");
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const long N = dims->N;
+  if (dims->ndim >= 2) {
+    const size_t ts = (dtype == USP_C128 && !refine) ? 16 : 8;
+    lay->t = take(N * ts);
+    lay->S = take(N * 16);
+    if (refine) {
+      lay->B32 = take(N * 8);
+      lay->r32 = take(N * 8);
+      lay->d32 = take(N * 8);
+    }
+  }
+  lay->nblk = (long)dims->n0 * dims->n1 + 4096;
+  lay->partials = take(sizeof(double) * lay->nblk);
+  lay->counters = take(64 * sizeof(unsigned));
+  lay->slots = take(64 * sizeof(int));
+  lay->hist = take(sizeof(double) * kHist);
+  lay->scal = take(64 * sizeof(double));
+  lay->hist_true = take(2 * sizeof(double) * kHist);
+  lay->info = take(64);
+  for (int l = 3; l <= 10; ++l) {
+    const int n = 1 << l;
+    if (n == dims->n0 || n == dims->n1 || n == dims->n2) {
+      lay->twf[l] = take(sizeof(float2) * n);
+      lay->twd[l] = take(sizeof(double2) * n);
+    }
+  }
+  lay->q0 = take(sizeof(double) * dims->n0);
+  lay->q1 = take(sizeof(double) * dims->n1);
+  lay->q2 = take(sizeof(double) * dims->n2);
+  lay->qzero = take(sizeof(double) * 8);
+  lay->total = off;
+  return 0;
+}
+
+}  // namespace
+
+struct usp_op_s {
+  Dims d;
+  int dtype = 0, flags = 0;
+  bool refine = false;
+  hipStream_t st = nullptr;
+  usp_symbol sym;
+  const void* B = nullptr;
+  bool has_gather = false;
+  usp_gather g{};
+  char* ws = nullptr;
+  Layout lay;
+  void* t = nullptr;
+  double2* S = nullptr;
+  float2 *B32 = nullptr, *r32 = nullptr, *d32 = nullptr;
+  double* partials = nullptr;
+  unsigned* counters = nullptr;
+  int* slots = nullptr;
+  double* hist = nullptr;
+  double* scal = nullptr;
+  double* hist_true = nullptr;
+  Solve1DInfo* info = nullptr;
+  float2* twf[11] = {nullptr};
+  double2* twd[11] = {nullptr};
+  double *q0 = nullptr, *q1 = nullptr, *q2 = nullptr, *qzero = nullptr;
+  // symbol multiplier constants
+  double sa0[2], sa1[2], sa2[2];
+};
+
+namespace {
+
+template <class C> C* tw_for(usp_op op, int n);
+template <> float2* tw_for<float2>(usp_op op, int n) { return op->twf[ilog2(n)]; }
+template <> double2* tw_for<double2>(usp_op op, int n) { return op->twd[ilog2(n)]; }
+
+RedArgs red_args(usp_op op, double* out, int* slot, int nslots) {
+  RedArgs r;
+  r.partials = op->partials;
+  r.counter = op->counters;
+  r.out = out;
+  r.slot = slot;
+  r.nslots = nslots;
+  return r;
+}
+
+// ---- pass launchers --------------------------------------------------------
+template <class Cc, class Cx, int MODE>
+int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d, float2* r32, double alpha,
+             int has_x, RedArgs red) {
+  const Dims& D = op->d;
+  const int nlines = D.n0 * D.n1;
+  bool ok = with_n(D.n2, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int E = PassPlan<N>::E, T = N / E;
+    constexpr int TPB = x_threads<Cc>();
+    constexpr int LPB = TPB / T;
+    const int blocks = (nlines + LPB - 1) / LPB;
+    hipLaunchKernelGGL((k_xpass<Cc, Cx, N, MODE>), dim3(blocks), dim3(TPB), 0, op->st, t, x, y, B, d, r32,
+                       tw_for<Cc>(op, N), alpha, nlines, has_x, red);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
+  LAUNCHCHK("k_xpass");
+  return 0;
+}
+
+template <class C, int N> constexpr int pick_w() {
+  if constexpr (sizeof(C) == 8) return N >= 1024 ? 8 : 16;
+  else return N >= 1024 ? 4 : 8;
+}
+
+// strided pass along axis 0 (ax = 0) or axis 1 (ax = 1, 3-D only)
+template <class C, int MODE>
+int launch_s(usp_op op, C* data, int ax, const SymArgs& sym) {
+  const Dims& D = op->d;
+  const int n = ax == 0 ? D.n0 : D.n1;
+  const long S = ax == 0 ? (long)D.n1 * D.n2 : (long)D.n2;
+  const int batch = ax == 0 ? 1 : D.n0;
+  bool ok = with_n(n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int E = PassPlan<N>::E, T = N / E;
+    constexpr int Wd = pick_w<C, N>();
+    if (S >= Wd) {
+      hipLaunchKernelGGL((k_spass<C, N, Wd, MODE>), dim3((unsigned)(S / Wd), batch), dim3(Wd * T), 0, op->st,
+                         data, tw_for<C>(op, N), S, sym);
+    } else {
+      constexpr int W8 = 8;
+      hipLaunchKernelGGL((k_spass<C, N, W8, MODE>), dim3((unsigned)(S / W8), batch), dim3(W8 * T), 0, op->st,
+                         data, tw_for<C>(op, N), S, sym);
+    }
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "strided axis length");
+  LAUNCHCHK("k_spass");
+  return 0;
+}
+
+SymArgs sym_args(usp_op op, bool plus_one) {
+  SymArgs a;
+  a.qa = op->q0;
+  a.qm = op->d.ndim == 3 ? op->q1 : op->qzero;
+  a.qx = op->q2;
+  a.log2_n2 = ilog2(op->d.n2);
+  a.c0r = op->sa0[0] + (plus_one ? 1.0 : 0.0);
+  a.c0i = op->sa0[1];
+  a.c2r = op->sa2[0];
+  a.c2i = op->sa2[1];
+  a.scale = 1.0 / (double)op->d.N;
+  return a;
+}
+
+// Forward FFT (axis n2) of the first t = B x + y.
+template <class C>
+int first_pass(usp_op op, C* x, const C* y, const C* B, int has_x) {
+  return launch_x<C, C, X_FIRST>(op, (C*)op->t, x, y, B, nullptr, nullptr, 0.0, has_x,
+                                 red_args(op, nullptr, nullptr, 0));
+}
+
+// Middle passes of one iteration plus the fused update/first pass of the next.
+template <class C>
+int iteration(usp_op op, C* x, const C* y, const C* B, double alpha) {
+  C* t = (C*)op->t;
+  const SymArgs sa = sym_args(op, true);
+  int rc;
+  if (op->d.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa))) return rc;
+  if ((rc = launch_s<C, S_SYM>(op, t, 0, sa))) return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa))) return rc;
+  return launch_x<C, C, X_FUSED>(op, t, x, y, B, nullptr, nullptr, alpha, 1,
+                                 red_args(op, op->hist, op->slots, kHist));
+}
+
+// FP64 true residual of x (storage Cx); ||r||^2 -> scal[0].  d: correction added
+// into x first (refinement), r32: complex64 copy of r (refinement).
+template <class Cx>
+int residual_passes(usp_op op, Cx* x, const Cx* y, const Cx* B, const float2* d, float2* r32) {
+  double2* S = op->S;
+  const SymArgs sa = sym_args(op, false);
+  int rc;
+  if ((rc = launch_x<double2, Cx, X_RFWD>(op, S, x, y, B, d, nullptr, 0.0, 0, red_args(op, nullptr, nullptr, 0))))
+    return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<double2, S_FWD>(op, S, 1, sa))) return rc;
+  if ((rc = launch_s<double2, S_SYMA>(op, S, 0, sa))) return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<double2, S_INV>(op, S, 1, sa))) return rc;
+  return launch_x<double2, Cx, X_RINV>(op, S, x, y, B, nullptr, r32, 0.0, 0, red_args(op, op->scal, nullptr, 0));
+}
+
+template <class C>
+int norm2(usp_op op, const C* z, double* out) {
+  const long n = op->d.N;
+  int blocks = (int)std::min<long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL((k_norm2<C>), dim3(blocks), dim3(256), 0, op->st, z, n, op->partials, op->counters, out);
+  LAUNCHCHK("k_norm2");
+  return 0;
+}
+
+Sym1D sym1d(usp_op op) {
+  Sym1D s;
+  s.c0r = op->sa0[0]; s.c0i = op->sa0[1];
+  s.c1r = op->sa1[0]; s.c1i = op->sa1[1];
+  s.c2r = op->sa2[0]; s.c2i = op->sa2[1];
+  s.pscale = 2.0 * M_PI / (op->d.n2 * op->sym.spacing[0]);
+  s.nyq_zero = op->sym.nyquist_zero;
+  return s;
+}
+
+// ---- host-side bookkeeping of a solve ---------------------------------------
+struct Monitor {
+  double* hist_pre;
+  int hist_pre_cap;
+  double* hist_true;
+  int hist_true_cap;
+  int n_true = 0;
+  double best = INFINITY;
+  int since_best = 0;
+  double d_first = -1.0, d_prev = -1.0;
+  int grow = 0;
+  bool diverged = false, nan = false;
+
+  void delta(int it, double dd) {
+    if (hist_pre && it < hist_pre_cap) hist_pre[it] = dd;
+    if (!(dd == dd)) nan = true;
+    if (d_first < 0) d_first = dd;
+    grow = (d_prev >= 0 && dd > d_prev) ? grow + 1 : 0;
+    d_prev = dd;
+    if (grow >= 3 && dd > d_first) diverged = true;
+  }
+  // returns true if stagnated
+  bool check(int it, double rho) {
+    if (hist_true && n_true < hist_true_cap) {
+      hist_true[2 * n_true] = it;
+      hist_true[2 * n_true + 1] = rho;
+    }
+    ++n_true;
+    if (!(rho == rho)) nan = true;
+    if (rho < 0.99 * best) {
+      best = rho;
+      since_best = 0;
+    } else {
+      ++since_best;
+    }
+    return since_best >= 8;
+  }
+};
+
+// copy ring entries [from, to) of ||Delta||^2 to the monitor
+int pull_hist(usp_op op, int from, int to, Monitor& mon, std::vector<double>& buf) {
+  if (to <= from) return 0;
+  const int n = to - from;
+  buf.resize(n);
+  int done = 0;
+  while (done < n) {
+    const int s = (from + done) % kHist;
+    const int cnt = std::min(n - done, kHist - s);
+    HIPCHK(hipMemcpyAsync(buf.data() + done, op->hist + s, cnt * sizeof(double), hipMemcpyDeviceToHost, op->st));
+    done += cnt;
+  }
+  HIPCHK(hipStreamSynchronize(op->st));
+  for (int i = 0; i < n; ++i) mon.delta(from + i, buf[i]);
+  return 0;
+}
+
+template <class C>
+int solve_plain(usp_op op, const C* y, C* x, int x_is_guess, double alpha, double tol, int maxit, int check_every,
+                int* iters_out, Monitor& mon, bool check_residual) {
+  int rc;
+  const C* B = (const C*)op->B;
+  if ((rc = norm2(op, y, op->scal + 1))) return rc;
+  HIPCHK(hipMemsetAsync(op->slots, 0, sizeof(int), op->st));
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * op->d.N, op->st));
+  if ((rc = first_pass<C>(op, x, y, B, x_is_guess))) return rc;
+  std::vector<double> buf;
+  int it = 0, pulled = 0, status = USP_MAXIT;
+  double host[2];
+  while (it < maxit) {
+    if ((rc = iteration<C>(op, x, y, B, alpha))) return rc;
+    ++it;
+    const bool chk = check_residual && (it % check_every == 0 || it == maxit);
+    if (chk) {
+      if ((rc = residual_passes<C>(op, x, y, B, nullptr, nullptr))) return rc;
+      HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+      if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
+      pulled = it;
+      const double rho = std::sqrt(host[0] / host[1]);
+      const bool stag = mon.check(it, rho);
+      if (mon.nan) { status = USP_ERR_NAN; break; }
+      if (rho < tol) { status = USP_OK; break; }
+      if (mon.diverged) { status = USP_DIVERGED; break; }
+      if (stag) { status = USP_STAGNATED; break; }
+    } else if (it - pulled >= kHist / 2) {
+      if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
+      pulled = it;
+    }
+  }
+  if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
+  HIPCHK(hipStreamSynchronize(op->st));
+  if (iters_out) *iters_out = it;
+  if (status == USP_MAXIT && mon.nan) status = USP_ERR_NAN;
+  if (status < 0) return fail(status, "non-finite values in the iteration");
+  return status;
+}
+
+int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, double alpha, double tol, int maxit,
+                  int k, int* iters_out, Monitor& mon) {
+  int rc;
+  const double2* B = (const double2*)op->B;
+  if ((rc = norm2(op, y, op->scal + 1))) return rc;
+  HIPCHK(hipMemsetAsync(op->slots, 0, sizeof(int), op->st));
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * op->d.N, op->st));
+  std::vector<double> buf;
+  int it = 0, pulled = 0, status = USP_MAXIT;
+  double host[2];
+  const float2* d = nullptr;
+  while (true) {
+    // r = y - A (x + d) in FP64; x <- x + d; r32 = complex64(r)
+    if ((rc = residual_passes<double2>(op, x, y, B, d, op->r32))) return rc;
+    HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+    if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
+    pulled = it;
+    const double rho = std::sqrt(host[0] / host[1]);
+    const bool stag = mon.check(it, rho);
+    if (mon.nan) { status = USP_ERR_NAN; break; }
+    if (rho < tol) { status = USP_OK; break; }
+    if (mon.diverged) { status = USP_DIVERGED; break; }
+    if (stag) { status = USP_STAGNATED; break; }
+    if (it >= maxit) break;
+    // inner complex64 iterations on A d = r from d = 0
+    const int m = std::min(k, maxit - it);
+    HIPCHK(hipMemsetAsync(op->d32, 0, sizeof(float2) * op->d.N, op->st));
+    if ((rc = first_pass<float2>(op, op->d32, op->r32, op->B32, 0))) return rc;
+    for (int j = 0; j < m; ++j)
+      if ((rc = iteration<float2>(op, op->d32, op->r32, op->B32, alpha))) return rc;
+    it += m;
+    d = op->d32;
+  }
+  HIPCHK(hipStreamSynchronize(op->st));
+  if (iters_out) *iters_out = it;
+  if (status < 0) return fail(status, "non-finite values in the iteration");
+  return status;
+}
+
+template <class C>
+int solve_1d(usp_op op, const C* y, C* x, int x_is_guess, double alpha, double tol, int maxit, int check_every,
+             int* iters_out, Monitor& mon) {
+  const int n = op->d.n2;
+  const int* gi = op->has_gather ? op->g.idx_dev : nullptr;
+  const C* g0 = op->has_gather ? (const C*)op->g.g0_dev : nullptr;
+  const C* g1 = op->has_gather ? (const C*)op->g.g1_dev : nullptr;
+  const Sym1D s = sym1d(op);
+  bool ok = with_n(n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int T = N / LinePlan<N>::E;
+    hipLaunchKernelGGL((k_solve1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
+                       tw_for<C>(op, N), s, alpha, tol, maxit, check_every, x_is_guess, op->hist, op->hist_true,
+                       kHist, op->info);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "1-D length");
+  LAUNCHCHK("k_solve1d");
+  Solve1DInfo info;
+  HIPCHK(hipMemcpyAsync(&info, op->info, sizeof(info), hipMemcpyDeviceToHost, op->st));
+  HIPCHK(hipStreamSynchronize(op->st));
+  const int nh = std::min(info.iterations, kHist);
+  std::vector<double> hp(nh);
+  if (nh) HIPCHK(hipMemcpy(hp.data(), op->hist, nh * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < nh; ++i)
+    if (mon.hist_pre && i < mon.hist_pre_cap) mon.hist_pre[i] = hp[i];
+  const int nt = std::min(info.n_true, kHist);
+  std::vector<double> ht(2 * nt);
+  if (nt) HIPCHK(hipMemcpy(ht.data(), op->hist_true, 2 * nt * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < nt && mon.hist_true && i < mon.hist_true_cap; ++i) {
+    mon.hist_true[2 * i] = ht[2 * i];
+    mon.hist_true[2 * i + 1] = ht[2 * i + 1];
+  }
+  mon.n_true = info.n_true;
+  if (iters_out) *iters_out = info.iterations;
+  if (info.status == -5) return fail(USP_ERR_NAN, "non-finite values in the iteration");
+  return info.status;
+}
+
+template <class C>
+int residual_1d(usp_op op, const C* y, const C* x, double* out2) {
+  const int n = op->d.n2;
+  const int* gi = op->has_gather ? op->g.idx_dev : nullptr;
+  const C* g0 = op->has_gather ? (const C*)op->g.g0_dev : nullptr;
+  const C* g1 = op->has_gather ? (const C*)op->g.g1_dev : nullptr;
+  const Sym1D s = sym1d(op);
+  bool ok = with_n(n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int T = N / LinePlan<N>::E;
+    hipLaunchKernelGGL((k_residual1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
+                       op->twd[ilog2(N)], s, op->scal);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "1-D length");
+  LAUNCHCHK("k_residual1d");
+  HIPCHK(hipMemcpyAsync(out2, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+  HIPCHK(hipStreamSynchronize(op->st));
+  return 0;
+}
+
+void cmulh(const double a[2], const double b[2], double out[2]) {
+  const double r = a[0] * b[0] - a[1] * b[1], i = a[0] * b[1] + a[1] * b[0];
+  out[0] = r;
+  out[1] = i;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* usp_last_error(void) { return g_err.c_str(); }
+
+int usp_workspace_bytes(const usp_symbol* L, int dtype, int flags, size_t* bytes) {
+  Layout lay;
+  Dims d;
+  int rc = make_layout(L, dtype, flags, &lay, &d);
+  if (rc) return rc;
+  if (!bytes) return fail(USP_ERR_INVALID, "bytes is NULL");
+  *bytes = lay.total;
+  return 0;
+}
+
+int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* B_dev, const usp_gather* gather,
+                         void* workspace_dev, size_t workspace_bytes, void* stream, usp_op* out) {
+  if (!out) return fail(USP_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  Layout lay;
+  Dims d;
+  int rc = make_layout(L, dtype, flags, &lay, &d);
+  if (rc) return rc;
+  if (!B_dev) return fail(USP_ERR_INVALID, "B_dev is NULL");
+  if (!workspace_dev || workspace_bytes < lay.total)
+    return fail(USP_ERR_WORKSPACE, "workspace too small: need " + std::to_string(lay.total) + " bytes");
+  if (((uintptr_t)workspace_dev) & 255) return fail(USP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (gather && d.ndim != 1) return fail(USP_ERR_INVALID, "a gather term needs ndim == 1");
+  if (gather && (!gather->idx_dev || !gather->g0_dev || !gather->g1_dev))
+    return fail(USP_ERR_INVALID, "gather arrays must be non-NULL");
+
+  usp_op op = new usp_op_s();
+  op->d = d;
+  op->dtype = dtype;
+  op->flags = flags;
+  op->refine = (flags & USP_FLAG_REFINE) != 0;
+  op->st = (hipStream_t)stream;
+  op->sym = *L;
+  op->B = B_dev;
+  op->has_gather = gather != nullptr;
+  if (gather) op->g = *gather;
+  op->ws = (char*)workspace_dev;
+  op->lay = lay;
+  char* w = op->ws;
+  if (d.ndim >= 2) {
+    op->t = w + lay.t;
+    op->S = (double2*)(w + lay.S);
+    if (op->refine) {
+      op->B32 = (float2*)(w + lay.B32);
+      op->r32 = (float2*)(w + lay.r32);
+      op->d32 = (float2*)(w + lay.d32);
+    }
+  }
+  op->partials = (double*)(w + lay.partials);
+  op->counters = (unsigned*)(w + lay.counters);
+  op->slots = (int*)(w + lay.slots);
+  op->hist = (double*)(w + lay.hist);
+  op->scal = (double*)(w + lay.scal);
+  op->hist_true = (double*)(w + lay.hist_true);
+  op->info = (Solve1DInfo*)(w + lay.info);
+  op->q0 = (double*)(w + lay.q0);
+  op->q1 = (double*)(w + lay.q1);
+  op->q2 = (double*)(w + lay.q2);
+  op->qzero = (double*)(w + lay.qzero);
+  cmulh(L->s, L->a0, op->sa0);
+  cmulh(L->s, L->a1, op->sa1);
+  cmulh(L->s, L->a2, op->sa2);
+
+  auto cleanup = [&](int code) {
+    delete op;
+    return code;
+  };
+  // twiddle tables exp(-2 pi i k / n), computed in long double
+  for (int l = 3; l <= 10; ++l) {
+    const int n = 1 << l;
+    if (!lay.twd[l]) continue;
+    std::vector<float2> tf(n);
+    std::vector<double2> td(n);
+    for (int k = 0; k < n; ++k) {
+      const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)n;
+      const long double c = cosl(a), s = sinl(a);
+      td[k].x = (double)c;
+      td[k].y = (double)s;
+      tf[k].x = (float)c;
+      tf[k].y = (float)s;
+    }
+    op->twf[l] = (float2*)(w + lay.twf[l]);
+    op->twd[l] = (double2*)(w + lay.twd[l]);
+    if (hipMemcpyAsync(op->twf[l], tf.data(), n * sizeof(float2), hipMemcpyHostToDevice, op->st) != hipSuccess ||
+        hipMemcpyAsync(op->twd[l], td.data(), n * sizeof(double2), hipMemcpyHostToDevice, op->st) != hipSuccess ||
+        hipStreamSynchronize(op->st) != hipSuccess)
+      return cleanup(fail(USP_ERR_HIP, "twiddle upload failed"));
+  }
+  // (p_axis)^2 tables: p_k = 2 pi fftfreq(n, h)
+  {
+    const int ns[3] = {d.n0, d.n1, d.n2};
+    double* dst[3] = {op->q0, op->q1, op->q2};
+    // spacing per internal axis
+    double hs[3];
+    if (d.ndim == 1) { hs[0] = hs[1] = 1.0; hs[2] = L->spacing[0]; }
+    else if (d.ndim == 2) { hs[0] = L->spacing[0]; hs[1] = 1.0; hs[2] = L->spacing[1]; }
+    else { hs[0] = L->spacing[0]; hs[1] = L->spacing[1]; hs[2] = L->spacing[2]; }
+    for (int a = 0; a < 3; ++a) {
+      std::vector<double> q(ns[a]);
+      for (int k = 0; k < ns[a]; ++k) {
+        const int kk = (k < (ns[a] + 1) / 2) ? k : k - ns[a];
+        const double p = (ns[a] == 1) ? 0.0 : 2.0 * M_PI * kk / (ns[a] * hs[a]);
+        q[k] = p * p;
+      }
+      if (hipMemcpyAsync(dst[a], q.data(), ns[a] * sizeof(double), hipMemcpyHostToDevice, op->st) != hipSuccess)
+        return cleanup(fail(USP_ERR_HIP, "table upload failed"));
+    }
+    std::vector<double> z(8, 0.0);
+    if (hipMemcpyAsync(op->qzero, z.data(), 8 * sizeof(double), hipMemcpyHostToDevice, op->st) != hipSuccess ||
+        hipStreamSynchronize(op->st) != hipSuccess)
+      return cleanup(fail(USP_ERR_HIP, "table upload failed"));
+  }
+  if (hipMemsetAsync(op->counters, 0, 64 * sizeof(unsigned), op->st) != hipSuccess ||
+      hipMemsetAsync(op->slots, 0, 64 * sizeof(int), op->st) != hipSuccess)
+    return cleanup(fail(USP_ERR_HIP, "workspace init failed"));
+  if (op->refine) {
+    hipLaunchKernelGGL(k_to_c64, dim3(1024), dim3(256), 0, op->st, (const double2*)B_dev, op->B32, d.N);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(USP_ERR_HIP, "k_to_c64 launch failed"));
+  }
+  // ||V|| < 1 (diagonal part): max |1 - B|
+  {
+    const int blocks = (int)std::min<long>((d.N + 255) / 256, 1024);
+    if (dtype == USP_C64)
+      hipLaunchKernelGGL((k_max_v<float2>), dim3(blocks), dim3(256), 0, op->st, (const float2*)B_dev, d.N, op->partials);
+    else
+      hipLaunchKernelGGL((k_max_v<double2>), dim3(blocks), dim3(256), 0, op->st, (const double2*)B_dev, d.N,
+                         op->partials);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(256), 0, op->st, op->partials, blocks, op->scal + 2);
+    if (hipGetLastError() != hipSuccess) return cleanup(fail(USP_ERR_HIP, "k_max_v launch failed"));
+    double vmax = 0;
+    if (hipMemcpyAsync(&vmax, op->scal + 2, sizeof(double), hipMemcpyDeviceToHost, op->st) != hipSuccess ||
+        hipStreamSynchronize(op->st) != hipSuccess)
+      return cleanup(fail(USP_ERR_HIP, "max|v| readback failed"));
+    if (!(vmax < 1.0))
+      return cleanup(fail(USP_ERR_NOT_CONTRACTIVE, "max|v| = " + std::to_string(vmax) + " is not < 1"));
+  }
+  *out = op;
+  return 0;
+}
+
+int usp_destroy(usp_op op) {
+  delete op;
+  return 0;
+}
+
+int usp_solve(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double alpha, double tol, int maxit,
+              int check_every, int* iters_out, double* hist_pre, int hist_pre_cap, double* hist_true,
+              int hist_true_cap, int* n_true_out) {
+  if (!op || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  if (!(alpha > 0.0) || maxit < 0 || check_every < 1) return fail(USP_ERR_INVALID, "alpha > 0, maxit >= 0, check_every >= 1");
+  Monitor mon{hist_pre, hist_pre_cap, hist_true, hist_true_cap};
+  int rc;
+  if (op->d.ndim == 1) {
+    if (op->dtype == USP_C64)
+      rc = solve_1d<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, alpha, tol, maxit, check_every,
+                            iters_out, mon);
+    else
+      rc = solve_1d<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, tol, maxit,
+                             check_every, iters_out, mon);
+  } else if (op->refine) {
+    rc = solve_refined(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, tol, maxit, check_every,
+                       iters_out, mon);
+  } else if (op->dtype == USP_C64) {
+    rc = solve_plain<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, alpha, tol, maxit, check_every,
+                             iters_out, mon, true);
+  } else {
+    rc = solve_plain<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, tol, maxit,
+                              check_every, iters_out, mon, true);
+  }
+  if (n_true_out) *n_true_out = mon.n_true;
+  return rc;
+}
+
+int usp_iterate(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double alpha, int K, double* hist_pre,
+                int hist_pre_cap) {
+  if (!op || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  if (op->refine) return fail(USP_ERR_INVALID, "usp_iterate is not available in refined mode");
+  if (K < 0) return fail(USP_ERR_INVALID, "K >= 0");
+  Monitor mon{hist_pre, hist_pre_cap, nullptr, 0};
+  int it = 0, rc;
+  if (op->d.ndim == 1) {
+    if (op->dtype == USP_C64)
+      rc = solve_1d<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, alpha, -1.0, K, K + 1, &it, mon);
+    else
+      rc = solve_1d<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, -1.0, K, K + 1, &it,
+                             mon);
+  } else if (op->dtype == USP_C64) {
+    rc = solve_plain<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, alpha, -1.0, K, K + 1, &it, mon,
+                             false);
+  } else {
+    rc = solve_plain<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, -1.0, K, K + 1, &it,
+                              mon, false);
+  }
+  if (rc < 0) return rc;
+  return 0;
+}
+
+int usp_residual(usp_op op, const void* y_dev, const void* x_dev, double* rel_out, double* rnorm_out,
+                 double* ynorm_out) {
+  if (!op || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  double host[2];
+  int rc;
+  if (op->d.ndim == 1) {
+    rc = op->dtype == USP_C64 ? residual_1d<float2>(op, (const float2*)y_dev, (const float2*)x_dev, host)
+                              : residual_1d<double2>(op, (const double2*)y_dev, (const double2*)x_dev, host);
+    if (rc) return rc;
+  } else {
+    if (op->dtype == USP_C64 && !op->refine) {
+      if ((rc = norm2(op, (const float2*)y_dev, op->scal + 1))) return rc;
+      rc = residual_passes<float2>(op, (float2*)x_dev, (const float2*)y_dev, (const float2*)op->B, nullptr, nullptr);
+    } else {
+      if ((rc = norm2(op, (const double2*)y_dev, op->scal + 1))) return rc;
+      rc = residual_passes<double2>(op, (double2*)x_dev, (const double2*)y_dev, (const double2*)op->B, nullptr,
+                                    nullptr);
+    }
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+  }
+  if (rel_out) *rel_out = std::sqrt(host[0] / host[1]);
+  if (rnorm_out) *rnorm_out = std::sqrt(host[0]);
+  if (ynorm_out) *ynorm_out = std::sqrt(host[1]);
+  return 0;
+}
+
+int usp_canonical_fields(const void* q_dev, const void* S_dev, size_t n, const double* bias, const double* c,
+                         double src_scale, int dtype, void* B_dev, void* y_dev, void* stream) {
+  if (!q_dev || !S_dev || !bias || !c) return fail(USP_ERR_INVALID, "NULL argument");
+  if (c[0] == 0.0 && c[1] == 0.0) return fail(USP_ERR_INVALID, "c must be non-zero");
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  if (dtype == USP_C64)
+    hipLaunchKernelGGL((k_canonical_fields<float2>), dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const double2*)q_dev, (const double2*)S_dev, (long)n, bias[0], bias[1], c[0], c[1],
+                       src_scale, (float2*)B_dev, (float2*)y_dev);
+  else if (dtype == USP_C128)
+    hipLaunchKernelGGL((k_canonical_fields<double2>), dim3(blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const double2*)q_dev, (const double2*)S_dev, (long)n, bias[0], bias[1], c[0], c[1],
+                       src_scale, (double2*)B_dev, (double2*)y_dev);
+  else
+    return fail(USP_ERR_INVALID, "dtype");
+  LAUNCHCHK("k_canonical_fields");
+  return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Host canonicalisation helpers (Sec. 2.2, 3.1): the smallest disc enclosing the
+// diagonal entries of the raw V0 gives the bias (its centre) and, divided by
+// 0.95, the scale |c|.
+//
+// Complex centre: Welzl's randomised incremental algorithm (expected linear
+// time), run over the points in a seeded random order.  Real-axis centre:
+// golden-section search of the convex function b -> max_j |z_j - b|.
+#include <algorithm>
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "../../include/usp.h"
+
+namespace {
+
+struct Pt {
+  double x, y;
+};
+struct Circle {
+  double x, y, r;
+};
+
+inline bool inside(const Circle& c, const Pt& p) {
+  const double dx = p.x - c.x, dy = p.y - c.y;
+  const double d = std::sqrt(dx * dx + dy * dy);
+  return d <= c.r * (1.0 + 1e-12) + 1e-300;
+}
+
+Circle from2(const Pt& a, const Pt& b) {
+  const double cx = 0.5 * (a.x + b.x), cy = 0.5 * (a.y + b.y);
+  return {cx, cy, 0.5 * std::hypot(a.x - b.x, a.y - b.y)};
+}
+
+Circle from3(const Pt& a, const Pt& b, const Pt& c) {
+  // circumcircle via the perpendicular-bisector linear system, relative to a
+  const double bx = b.x - a.x, by = b.y - a.y, cx = c.x - a.x, cy = c.y - a.y;
+  const double d = 2.0 * (bx * cy - by * cx);
+  if (std::fabs(d) < 1e-300) {
+    // collinear: the widest pair
+    Circle c1 = from2(a, b), c2 = from2(a, c), c3 = from2(b, c);
+    if (c1.r >= c2.r && c1.r >= c3.r) return c1;
+    return c2.r >= c3.r ? c2 : c3;
+  }
+  const double b2 = bx * bx + by * by, c2 = cx * cx + cy * cy;
+  const double ux = (cy * b2 - by * c2) / d, uy = (bx * c2 - cx * b2) / d;
+  return {a.x + ux, a.y + uy, std::hypot(ux, uy)};
+}
+
+Circle welzl(std::vector<Pt>& p) {
+  std::mt19937_64 rng(12345);
+  std::shuffle(p.begin(), p.end(), rng);
+  const size_t n = p.size();
+  Circle c{p[0].x, p[0].y, 0.0};
+  for (size_t i = 1; i < n; ++i) {
+    if (inside(c, p[i])) continue;
+    c = {p[i].x, p[i].y, 0.0};
+    for (size_t j = 0; j < i; ++j) {
+      if (inside(c, p[j])) continue;
+      c = from2(p[i], p[j]);
+      for (size_t k = 0; k < j; ++k) {
+        if (inside(c, p[k])) continue;
+        c = from3(p[i], p[j], p[k]);
+      }
+    }
+  }
+  return c;
+}
+
+double farthest(const std::vector<Pt>& p, double bx, double by) {
+  double m = 0.0;
+  for (const Pt& q : p) m = std::max(m, (q.x - bx) * (q.x - bx) + (q.y - by) * (q.y - by));
+  return std::sqrt(m);
+}
+
+}  // namespace
+
+extern "C" int usp_smallest_circle(const double* pts, size_t n, int kind, double* centre_out, double* radius_out) {
+  if (!pts || !centre_out || !radius_out || n == 0) return USP_ERR_INVALID;
+  // de-duplicate (media hold few distinct values)
+  std::vector<Pt> p(n);
+  for (size_t i = 0; i < n; ++i) p[i] = {pts[2 * i], pts[2 * i + 1]};
+  std::sort(p.begin(), p.end(), [](const Pt& a, const Pt& b) { return a.x < b.x || (a.x == b.x && a.y < b.y); });
+  p.erase(std::unique(p.begin(), p.end(), [](const Pt& a, const Pt& b) { return a.x == b.x && a.y == b.y; }),
+          p.end());
+  for (const Pt& q : p)
+    if (!std::isfinite(q.x) || !std::isfinite(q.y)) return USP_ERR_NAN;
+  if (kind == USP_BIAS_COMPLEX) {
+    Circle c = welzl(p);
+    centre_out[0] = c.x;
+    centre_out[1] = c.y;
+    *radius_out = farthest(p, c.x, c.y);
+    return 0;
+  }
+  if (kind == USP_BIAS_REAL) {
+    double lo = p.front().x, hi = p.back().x;
+    const double g = 0.5 * (std::sqrt(5.0) - 1.0);
+    double a = hi - g * (hi - lo), b = lo + g * (hi - lo);
+    double fa = farthest(p, a, 0.0), fb = farthest(p, b, 0.0);
+    for (int it = 0; it < 200 && (hi - lo) > 1e-15 * (1.0 + std::fabs(lo) + std::fabs(hi)); ++it) {
+      if (fa <= fb) {
+        hi = b; b = a; fb = fa;
+        a = hi - g * (hi - lo);
+        fa = farthest(p, a, 0.0);
+      } else {
+        lo = a; a = b; fa = fb;
+        b = lo + g * (hi - lo);
+        fb = farthest(p, b, 0.0);
+      }
+    }
+    const double bc = 0.5 * (lo + hi);
+    centre_out[0] = bc;
+    centre_out[1] = 0.0;
+    *radius_out = farthest(p, bc, 0.0);
+    return 0;
+  }
+  return USP_ERR_INVALID;
+}
+
+namespace {
+int fill_grid(const usp_symbol* grid, usp_symbol* out) {
+  if (!grid || !out) return USP_ERR_INVALID;
+  *out = *grid;
+  out->s[0] = out->s[1] = out->a0[0] = out->a0[1] = out->a1[0] = out->a1[1] = out->a2[0] = out->a2[1] = 0.0;
+  out->nyquist_zero = 0;
+  return 0;
+}
+void cdiv(double ar, double ai, double br, double bi, double* o) {
+  const double d = br * br + bi * bi;
+  o[0] = (ar * br + ai * bi) / d;
+  o[1] = (ai * br - ar * bi) / d;
+}
+}  // namespace
+
+// Helmholtz (Sec. 3.1): (laplacian + k^2) psi = -S.  kbar^2 = smallest-circle
+// centre of {k^2} (or the best real centre), c = -R/(vnorm i) = i R / vnorm, so
+// that max|v| = vnorm and A = (laplacian + k^2)/c is accretive.  With `given`
+// (kbar^2 re, im, c re, im) both are taken from the caller.  Symbol:
+// l(p) = (-|p|^2 + kbar^2)/c.
+extern "C" int usp_canonical_helmholtz(const double* k2_host, size_t n, int bias_kind, const double* given,
+                                       double vnorm, const usp_symbol* grid, usp_symbol* sym_out, double* c_out,
+                                       double* bias_out) {
+  if (!c_out || !bias_out || !(vnorm > 0.0 && vnorm < 1.0)) return USP_ERR_INVALID;
+  int rc = fill_grid(grid, sym_out);
+  if (rc) return rc;
+  double centre[2], R = 0.0;
+  if (given) {
+    centre[0] = given[0];
+    centre[1] = given[1];
+    c_out[0] = given[2];
+    c_out[1] = given[3];
+  } else {
+    if (!k2_host) return USP_ERR_INVALID;
+    rc = usp_smallest_circle(k2_host, n, bias_kind, centre, &R);
+    if (rc) return rc;
+    if (!(R > 0.0)) return USP_ERR_INVALID;  // homogeneous medium: bias and c must be given
+    c_out[0] = 0.0;
+    c_out[1] = R / vnorm;
+  }
+  bias_out[0] = centre[0];
+  bias_out[1] = centre[1];
+  cdiv(1.0, 0.0, c_out[0], c_out[1], sym_out->s);
+  sym_out->a0[0] = centre[0];
+  sym_out->a0[1] = centre[1];
+  sym_out->a2[0] = -1.0;
+  return 0;
+}
+
+// Scalar frequency-domain diffusion with constant D (Sec. 3.2 with D constant,
+// e^{-i omega t}): A0 = -D laplacian + mu_a - i omega/v.  mubar = centre of the
+// smallest circle of the real mu_a values (their midrange), c = R/vnorm (real).
+// Symbol: l(p) = (D |p|^2 + mubar - i omega/v)/c.
+extern "C" int usp_canonical_diffusion(const double* mu_host, size_t n, double D, double omega_over_v, double vnorm,
+                                       const usp_symbol* grid, usp_symbol* sym_out, double* c_out,
+                                       double* bias_out) {
+  if (!mu_host || !c_out || !bias_out || n == 0 || !(vnorm > 0.0 && vnorm < 1.0)) return USP_ERR_INVALID;
+  int rc = fill_grid(grid, sym_out);
+  if (rc) return rc;
+  double lo = mu_host[0], hi = mu_host[0];
+  for (size_t i = 1; i < n; ++i) {
+    if (!std::isfinite(mu_host[i])) return USP_ERR_NAN;
+    lo = std::min(lo, mu_host[i]);
+    hi = std::max(hi, mu_host[i]);
+  }
+  const double pts[4] = {lo, 0.0, hi, 0.0};
+  double centre[2], R;
+  rc = usp_smallest_circle(pts, 2, USP_BIAS_COMPLEX, centre, &R);
+  if (rc) return rc;
+  if (!(R > 0.0)) return USP_ERR_INVALID;
+  c_out[0] = R / vnorm;
+  c_out[1] = 0.0;
+  bias_out[0] = centre[0];
+  bias_out[1] = 0.0;
+  sym_out->s[0] = 1.0 / c_out[0];
+  sym_out->a0[0] = centre[0];
+  sym_out->a0[1] = -omega_over_v;
+  sym_out->a2[0] = D;
+  return 0;
+}

@@ -1,0 +1,222 @@
+"""Thin Python layer over the C ABI (``include/usp.h``): argument marshalling only.
+
+PyTorch provides device memory (tensors) and the stream; every arithmetic step
+of canonicalisation (host C++ in the library + a device kernel) and of the
+iteration (HIP kernels) runs in ``libusp.so``.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["Operator", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
+           "canonical_diffusion", "canonical_fields"]
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ct.c_void_p(t.data_ptr())
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def _stream_ptr(device) -> ct.c_void_p:
+    return ct.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _c2(z) -> tuple:
+    z = complex(z)
+    return (z.real, z.imag)
+
+
+def make_symbol(shape, spacing, s=1.0, a0=0.0, a1=0.0, a2=0.0, nyquist_zero=False) -> L.usp_symbol:
+    """usp_symbol for l(p) = s (a0 + a2 |p|^2 + a1 i p) on a grid of ``shape``."""
+    sym = L.usp_symbol()
+    sym.ndim = len(shape)
+    for i, n in enumerate(shape):
+        sym.shape[i] = int(n)
+        sym.spacing[i] = float(spacing[i])
+    sym.s[:] = _c2(s)
+    sym.a0[:] = _c2(a0)
+    sym.a1[:] = _c2(a1)
+    sym.a2[:] = _c2(a2)
+    sym.nyquist_zero = int(bool(nyquist_zero))
+    return sym
+
+
+def symbol_coeffs(sym: L.usp_symbol) -> dict:
+    return {k: complex(getattr(sym, k)[0], getattr(sym, k)[1]) for k in ("s", "a0", "a1", "a2")}
+
+
+def smallest_circle(points, kind: str = "complex"):
+    """usp_smallest_circle on host points; returns (centre, radius)."""
+    pts = np.ascontiguousarray(np.asarray(points, dtype=np.complex128).ravel()).view(np.float64)
+    centre = np.zeros(2)
+    radius = np.zeros(1)
+    k = L.USP_BIAS_COMPLEX if kind == "complex" else L.USP_BIAS_REAL
+    L.check(L.lib().usp_smallest_circle(_dp(pts), pts.size // 2, k, _dp(centre), _dp(radius)))
+    return complex(centre[0], centre[1]), float(radius[0])
+
+
+def canonical_fields(q: torch.Tensor, S: torch.Tensor, bias, c, src_scale: float, dtype) -> tuple:
+    """B = 1 - (q - bias)/c and y = src_scale S / c on the device (usp_canonical_fields)."""
+    dev = q.device
+    n = q.numel()
+    B = torch.empty(q.shape, dtype=dtype, device=dev)
+    y = torch.empty(q.shape, dtype=dtype, device=dev)
+    dt = L.USP_C64 if dtype == torch.complex64 else L.USP_C128
+    b = np.array(_c2(bias))
+    cc = np.array(_c2(c))
+    L.check(L.lib().usp_canonical_fields(_ptr(q), _ptr(S), n, _dp(b), _dp(cc), float(src_scale), dt, _ptr(B),
+                                         _ptr(y), _stream_ptr(dev)))
+    return B, y
+
+
+@dataclass
+class Canonical:
+    symbol: L.usp_symbol
+    B: torch.Tensor
+    y: torch.Tensor
+    c: complex
+    bias: complex
+
+
+def canonical_helmholtz(k2, source, spacing, bias: str = "complex", given=None, vnorm: float = 0.95,
+                        dtype=torch.complex64, device="cuda") -> Canonical:
+    """Helmholtz canonical form (usp_canonical_helmholtz + usp_canonical_fields)."""
+    k2n = np.ascontiguousarray(np.asarray(k2, dtype=np.complex128))
+    shape = k2n.shape
+    grid = make_symbol(shape, spacing)
+    out = L.usp_symbol()
+    c = np.zeros(2)
+    b = np.zeros(2)
+    g = None if given is None else np.array(_c2(given[0]) + _c2(given[1]))
+    kind = L.USP_BIAS_COMPLEX if bias == "complex" else L.USP_BIAS_REAL
+    flat = k2n.ravel().view(np.float64)
+    L.check(L.lib().usp_canonical_helmholtz(_dp(flat), k2n.size, kind, None if g is None else _dp(g), vnorm,
+                                            ct.byref(grid), ct.byref(out), _dp(c), _dp(b)))
+    q = torch.from_numpy(k2n).to(device)
+    S = torch.from_numpy(np.ascontiguousarray(np.asarray(source, dtype=np.complex128))).to(device)
+    Bt, yt = canonical_fields(q, S, complex(b[0], b[1]), complex(c[0], c[1]), -1.0, dtype)
+    return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
+
+
+def canonical_diffusion(mu_a, D, omega_over_v, source, spacing, vnorm: float = 0.95, dtype=torch.complex64,
+                        device="cuda") -> Canonical:
+    """Constant-D diffusion canonical form (usp_canonical_diffusion + usp_canonical_fields)."""
+    mu = np.ascontiguousarray(np.asarray(mu_a, dtype=np.float64))
+    grid = make_symbol(mu.shape, spacing)
+    out = L.usp_symbol()
+    c = np.zeros(2)
+    b = np.zeros(2)
+    L.check(L.lib().usp_canonical_diffusion(_dp(mu.ravel()), mu.size, float(D), float(omega_over_v), vnorm,
+                                            ct.byref(grid), ct.byref(out), _dp(c), _dp(b)))
+    q = torch.from_numpy(mu.astype(np.complex128)).to(device)
+    S = torch.from_numpy(np.ascontiguousarray(np.asarray(source, dtype=np.complex128))).to(device)
+    Bt, yt = canonical_fields(q, S, complex(b[0], b[1]), complex(c[0], c[1]), 1.0, dtype)
+    return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor
+    iterations: int
+    status: int
+    hist_pre: np.ndarray = field(repr=False, default=None)     # ||Delta_i||^2
+    hist_true: np.ndarray = field(repr=False, default=None)    # (iteration, rho) rows
+
+    @property
+    def converged(self):
+        return self.status == L.USP_OK
+
+    @property
+    def status_name(self):
+        return L.STATUS_NAMES.get(self.status, str(self.status))
+
+
+class Operator:
+    """A prepared operator handle (usp_prepare_operator) with its workspace tensor."""
+
+    def __init__(self, symbol: L.usp_symbol, B: torch.Tensor, refine: bool = False, gather=None):
+        if not B.is_cuda:
+            raise ValueError("B must be a device tensor")
+        self.B = B
+        self.device = B.device
+        self.dtype = B.dtype
+        self.dt = L.USP_C64 if B.dtype == torch.complex64 else L.USP_C128
+        self.flags = L.USP_FLAG_REFINE if refine else 0
+        self.symbol = symbol
+        self.gather = gather   # keep device arrays alive
+        nbytes = ct.c_size_t()
+        L.check(L.lib().usp_workspace_bytes(ct.byref(symbol), self.dt, self.flags, ct.byref(nbytes)))
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=self.device)
+        g = None
+        if gather is not None:
+            idx, g0, g1 = gather
+            g = L.usp_gather(idx.data_ptr(), g0.data_ptr(), g1.data_ptr())
+        h = ct.c_void_p()
+        L.check(L.lib().usp_prepare_operator(ct.byref(symbol), self.dt, self.flags, _ptr(B),
+                                             None if g is None else ct.byref(g), _ptr(self.workspace),
+                                             nbytes.value, _stream_ptr(self.device), ct.byref(h)))
+        self.handle = h
+
+    @property
+    def shape(self):
+        return tuple(self.B.shape)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.lib().usp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field(self, t):
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != self.shape:
+            raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
+        return t
+
+    def solve(self, y, x=None, alpha=0.8, tol=1e-6, maxit=10000, check_every=20, hist_cap=None) -> SolveResult:
+        y = self._field(y)
+        guess = x is not None
+        x = self._field(x) if guess else torch.empty_like(y)
+        hc = maxit if hist_cap is None else hist_cap
+        hp = np.zeros(max(hc, 1))
+        ntc = maxit // check_every + 2
+        ht = np.zeros(2 * ntc)
+        it = ct.c_int()
+        nt = ct.c_int()
+        rc = L.check(L.lib().usp_solve(self.handle, _ptr(y), _ptr(x), int(guess), float(alpha), float(tol),
+                                       int(maxit), int(check_every), ct.byref(it), _dp(hp), hc, _dp(ht), ntc,
+                                       ct.byref(nt)))
+        n = min(it.value, hc)
+        m = min(nt.value, ntc)
+        return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:n].copy(),
+                           hist_true=ht[:2 * m].reshape(m, 2).copy())
+
+    def iterate(self, y, x=None, alpha=0.8, K=1):
+        """Exactly K iterations (test hook); returns (x, ||Delta_i||^2 array)."""
+        y = self._field(y)
+        guess = x is not None
+        x = self._field(x) if guess else torch.empty_like(y)
+        hp = np.zeros(max(K, 1))
+        L.check(L.lib().usp_iterate(self.handle, _ptr(y), _ptr(x), int(guess), float(alpha), int(K), _dp(hp), K))
+        return x, hp[:K].copy()
+
+    def residual(self, y, x):
+        """(||y - A x||/||y||, ||y - A x||, ||y||) in FP64."""
+        rel, rn, yn = np.zeros(1), np.zeros(1), np.zeros(1)
+        L.check(L.lib().usp_residual(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), _dp(rel), _dp(rn),
+                                     _dp(yn)))
+        return float(rel[0]), float(rn[0]), float(yn[0])

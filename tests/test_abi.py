@@ -1,0 +1,87 @@
+"""The C ABI library loads and exports every symbol include/usp.h declares (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "usp.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(usp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = declared()
+    for n in ("usp_prepare_operator", "usp_solve", "usp_workspace_bytes", "usp_destroy", "usp_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2207_14222_amd import _lib
+    L = _lib.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+    assert set(_lib.EXPORTS) == set(declared())
+
+
+def test_workspace_bytes_and_shape_validation():
+    from paper_2207_14222_amd import _lib, solver
+    L = _lib.lib()
+    sym = solver.make_symbol((64, 32, 16), (0.25,) * 3, s=1j, a0=2.0, a2=-1.0)
+    n = ctypes.c_size_t()
+    assert L.usp_workspace_bytes(ctypes.byref(sym), _lib.USP_C64, 0, ctypes.byref(n)) == 0
+    N = 64 * 32 * 16
+    assert n.value >= N * (8 + 16)
+    nr = ctypes.c_size_t()
+    assert L.usp_workspace_bytes(ctypes.byref(sym), _lib.USP_C128, _lib.USP_FLAG_REFINE, ctypes.byref(nr)) == 0
+    assert nr.value >= N * (8 + 16 + 3 * 8)
+    # refined mode requires complex128 buffers
+    assert L.usp_workspace_bytes(ctypes.byref(sym), _lib.USP_C64, _lib.USP_FLAG_REFINE, ctypes.byref(n)) == -1
+    bad = solver.make_symbol((64, 30, 16), (0.25,) * 3)
+    assert L.usp_workspace_bytes(ctypes.byref(bad), _lib.USP_C64, 0, ctypes.byref(n)) == _lib.USP_ERR_UNSUPPORTED_SHAPE
+    assert "power of two" in _lib.last_error()
+    big = solver.make_symbol((2048,), (0.25,))
+    assert L.usp_workspace_bytes(ctypes.byref(big), _lib.USP_C64, 0, ctypes.byref(n)) == _lib.USP_ERR_UNSUPPORTED_SHAPE
+
+
+def test_host_smallest_circle_matches_oracle():
+    """Host Welzl (library) against the oracle's exhaustive hull search."""
+    from oracle import canon
+    from paper_2207_14222_amd import solver
+    rng = np.random.default_rng(5)
+    for trial in range(5):
+        pts = rng.normal(size=300) * 5 + 1j * rng.normal(size=300) * (1 + trial)
+        z, r = solver.smallest_circle(pts)
+        zo, ro = canon.smallest_circle(pts)
+        assert abs(z - zo) < 1e-10 * (1 + abs(zo)) and abs(r - ro) < 1e-10 * ro
+        zr, rr = solver.smallest_circle(pts, "real")
+        zor, ror = canon.smallest_real_centre(pts)
+        assert abs(zr - zor) < 1e-7 * (1 + abs(zor)) and abs(rr - ror) < 1e-12 * ror
+
+
+def test_host_canonical_helmholtz_matches_oracle():
+    from oracle import canon
+    from paper_2207_14222_amd import _lib, media, solver
+    p = media.helmholtz_spheres(shape=(16, 16, 16), count=5, width=3, w0=3.0, plane=2)
+    k2 = np.ascontiguousarray(p.k2)
+    grid = solver.make_symbol(k2.shape, p.spacing)
+    out = _lib.usp_symbol()
+    c = np.zeros(2)
+    b = np.zeros(2)
+    flat = k2.ravel().view(np.float64)
+    rc = _lib.lib().usp_canonical_helmholtz(flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k2.size, 0, None,
+                                            0.95, ctypes.byref(grid), ctypes.byref(out),
+                                            c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            b.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert rc == 0
+    cp = canon.canonical_helmholtz(p.k2, p.source, p.spacing)
+    assert abs(complex(*c) - cp.c) < 1e-12 * abs(cp.c)
+    assert abs(complex(*b) - cp.bias) < 1e-12 * abs(cp.bias)
+    co = solver.symbol_coeffs(out)
+    assert abs(co["s"] - cp.s) < 1e-14 and co["a0"] == complex(*b) and co["a2"] == -1
