@@ -145,6 +145,29 @@ int usp_iterate(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, doubl
 int usp_residual(usp_op op, const void* y_dev, const void* x_dev, double* rel_out, double* rnorm_out,
                  double* ynorm_out);
 
+/* Per-pass timing with hipEvents on the handle's stream (2-D / 3-D grids).
+ * Runs the first pass and K iterations of Algorithm 1 from x = 0 on y_dev /
+ * x_dev (x_dev is overwritten) and one FP64 residual evaluation, with an event
+ * pair around every launch, then K more iterations bracketed by one event pair.
+ * In refined mode the iterations are the complex64 inner ones (on workspace
+ * copies; x_dev is the complex128 solution, only read) after one FP64 residual.
+ * pass_ms[USP_NPASS]: average milliseconds per launch of each pass kind (0 if
+ * the kind was not launched), indexed by USP_PASS_*; iter_ms (may be NULL):
+ * average milliseconds per whole iteration. */
+#define USP_NPASS 11
+#define USP_PASS_X_FUSED 0   /* inverse FFT (contiguous axis), update, norm, next forward FFT */
+#define USP_PASS_M_FWD 1     /* forward FFT along the middle axis (3-D) */
+#define USP_PASS_SYM 2       /* forward FFT, 1/(N (l + 1)), inverse FFT along the first axis */
+#define USP_PASS_M_INV 3     /* inverse FFT along the middle axis (3-D) */
+#define USP_PASS_X_FIRST 4   /* B x + y and its forward FFT (first iteration) */
+#define USP_PASS_R_FWD 5     /* FP64 residual: forward FFT of x (contiguous axis) */
+#define USP_PASS_R_MFWD 6
+#define USP_PASS_R_SYM 7     /* FP64 residual: forward FFT, l(p)/N, inverse FFT */
+#define USP_PASS_R_MINV 8
+#define USP_PASS_R_INV 9     /* FP64 residual: inverse FFT, r = y - A x, ||r||^2 */
+#define USP_PASS_REDUCE 10   /* ordered sum of per-block partial norms */
+int usp_profile(usp_op op, const void* y_dev, void* x_dev, double alpha, int K, double* pass_ms, double* iter_ms);
+
 /* Destroy a handle (frees host memory only). */
 int usp_destroy(usp_op op);
 

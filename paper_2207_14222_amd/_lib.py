@@ -24,7 +24,9 @@ STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "
 
 EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iterate", "usp_residual",
            "usp_destroy", "usp_last_error", "usp_smallest_circle", "usp_canonical_fields",
-           "usp_canonical_helmholtz", "usp_canonical_diffusion"]
+           "usp_canonical_helmholtz", "usp_canonical_diffusion", "usp_profile"]
+USP_NPASS = 11
+PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
 
 class usp_symbol(ct.Structure):
@@ -70,6 +72,7 @@ def lib():
     SP = ct.POINTER(usp_symbol)
     L.usp_canonical_helmholtz.argtypes = [DP, Z, I, DP, D, SP, SP, DP, DP]
     L.usp_canonical_diffusion.argtypes = [DP, Z, D, D, D, SP, SP, DP, DP]
+    L.usp_profile.argtypes = [P, P, P, D, I, DP, DP]
     for name in EXPORTS:
         if name != "usp_last_error":
             getattr(L, name).restype = ct.c_int

@@ -41,6 +41,7 @@ int fail(int code, const std::string& msg) {
   } while (0)
 
 constexpr int kHist = 1 << 16;   // device ring of ||Delta||^2 values
+constexpr int kRows = 32;        // pending per-iteration partial-sum rows between finalisations
 constexpr int kMinN = 8, kMaxN = 1024;
 
 bool pow2_in_range(int n) { return n >= kMinN && n <= kMaxN && (n & (n - 1)) == 0; }
@@ -69,7 +70,7 @@ size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
   size_t t = 0, S = 0, B32 = 0, r32 = 0, d32 = 0;
-  size_t partials = 0, counters = 0, slots = 0, hist = 0, scal = 0, hist_true = 0, info = 0;
+  size_t partials = 0, hist = 0, scal = 0, hist_true = 0, info = 0;
   size_t twf[11] = {0}, twd[11] = {0};
   size_t q0 = 0, q1 = 0, q2 = 0, qzero = 0;
   size_t total = 0;
@@ -123,10 +124,9 @@ int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, Dims* di
       lay->d32 = take(N * 8);
     }
   }
+  // one row of per-block partials per pending iteration, plus a residual row and a norm row
   lay->nblk = (long)dims->n0 * dims->n1 + 4096;
-  lay->partials = take(sizeof(double) * lay->nblk);
-  lay->counters = take(64 * sizeof(unsigned));
-  lay->slots = take(64 * sizeof(int));
+  lay->partials = take(sizeof(double) * lay->nblk * (kRows + 2));
   lay->hist = take(sizeof(double) * kHist);
   lay->scal = take(64 * sizeof(double));
   lay->hist_true = take(2 * sizeof(double) * kHist);
@@ -163,8 +163,10 @@ struct usp_op_s {
   double2* S = nullptr;
   float2 *B32 = nullptr, *r32 = nullptr, *d32 = nullptr;
   double* partials = nullptr;
-  unsigned* counters = nullptr;
-  int* slots = nullptr;
+  long pitch = 0;          // row pitch of partials (doubles)
+  int pending = 0;         // per-iteration rows written since the last finalisation
+  int pending_first = 0;   // iteration index of the first pending row
+  int xblocks = 0;         // blocks of the last complex64/128 contiguous-axis launch (row width)
   double* hist = nullptr;
   double* scal = nullptr;
   double* hist_true = nullptr;
@@ -174,22 +176,63 @@ struct usp_op_s {
   double *q0 = nullptr, *q1 = nullptr, *q2 = nullptr, *qzero = nullptr;
   // symbol multiplier constants
   double sa0[2], sa1[2], sa2[2];
+  // per-pass event timing (usp_profile)
+  std::vector<hipEvent_t>* prof = nullptr;  // array of USP_NPASS vectors of (start, stop) events
+  int kind = 0;
 };
 
 namespace {
+
+void prof_mark(usp_op op) {
+  if (!op->prof) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) == hipSuccess) {
+    hipEventRecord(e, op->st);
+    op->prof[op->kind].push_back(e);
+  }
+}
 
 template <class C> C* tw_for(usp_op op, int n);
 template <> float2* tw_for<float2>(usp_op op, int n) { return op->twf[ilog2(n)]; }
 template <> double2* tw_for<double2>(usp_op op, int n) { return op->twd[ilog2(n)]; }
 
-RedArgs red_args(usp_op op, double* out, int* slot, int nslots) {
+RedArgs red_row(usp_op op, int row) {
   RedArgs r;
-  r.partials = op->partials;
-  r.counter = op->counters;
-  r.out = out;
-  r.slot = slot;
-  r.nslots = nslots;
+  r.row = row < 0 ? nullptr : op->partials + (long)row * op->pitch;
   return r;
+}
+
+template <class Cc> int x_blocks(usp_op op) {
+  int nb = 0;
+  with_n(op->d.n2, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int LPB = x_threads<Cc>() / (N / PassPlan<N>::E);
+    nb = (op->d.n0 * op->d.n1 + LPB - 1) / LPB;
+  });
+  return nb;
+}
+
+// add up `nrows` partial rows starting at `row` (ncols partials each) into
+// out[(first + r) % nmod]
+int sum_rows(usp_op op, int row, int nrows, int ncols, double* out, int first, int nmod) {
+  if (nrows <= 0) return 0;
+  prof_mark(op);
+  hipLaunchKernelGGL(k_sum_rows, dim3(nrows), dim3(256), 0, op->st, op->partials + (long)row * op->pitch, op->pitch,
+                     ncols, out, first, nmod);
+  prof_mark(op);
+  LAUNCHCHK("k_sum_rows");
+  return 0;
+}
+
+// move pending per-iteration ||Delta||^2 partial rows into the history ring
+int finalize_hist(usp_op op) {
+  const int kind = op->kind;
+  op->kind = USP_PASS_REDUCE;
+  int rc = sum_rows(op, 0, op->pending, op->xblocks, op->hist, op->pending_first, kHist);
+  op->kind = kind;
+  op->pending_first += op->pending;
+  op->pending = 0;
+  return rc;
 }
 
 // ---- pass launchers --------------------------------------------------------
@@ -204,8 +247,11 @@ int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d,
     constexpr int TPB = x_threads<Cc>();
     constexpr int LPB = TPB / T;
     const int blocks = (nlines + LPB - 1) / LPB;
+    if (MODE == X_FUSED) op->xblocks = blocks;
+    prof_mark(op);
     hipLaunchKernelGGL((k_xpass<Cc, Cx, N, MODE>), dim3(blocks), dim3(TPB), 0, op->st, t, x, y, B, d, r32,
                        tw_for<Cc>(op, N), alpha, nlines, has_x, red);
+    prof_mark(op);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
   LAUNCHCHK("k_xpass");
@@ -228,6 +274,7 @@ int launch_s(usp_op op, C* data, int ax, const SymArgs& sym) {
     constexpr int N = decltype(NC)::value;
     constexpr int E = PassPlan<N>::E, T = N / E;
     constexpr int Wd = pick_w<C, N>();
+    prof_mark(op);
     if (S >= Wd) {
       hipLaunchKernelGGL((k_spass<C, N, Wd, MODE>), dim3((unsigned)(S / Wd), batch), dim3(Wd * T), 0, op->st,
                          data, tw_for<C>(op, N), S, sym);
@@ -236,6 +283,7 @@ int launch_s(usp_op op, C* data, int ax, const SymArgs& sym) {
       hipLaunchKernelGGL((k_spass<C, N, W8, MODE>), dim3((unsigned)(S / W8), batch), dim3(W8 * T), 0, op->st,
                          data, tw_for<C>(op, N), S, sym);
     }
+    prof_mark(op);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "strided axis length");
   LAUNCHCHK("k_spass");
@@ -259,8 +307,8 @@ SymArgs sym_args(usp_op op, bool plus_one) {
 // Forward FFT (axis n2) of the first t = B x + y.
 template <class C>
 int first_pass(usp_op op, C* x, const C* y, const C* B, int has_x) {
-  return launch_x<C, C, X_FIRST>(op, (C*)op->t, x, y, B, nullptr, nullptr, 0.0, has_x,
-                                 red_args(op, nullptr, nullptr, 0));
+  op->kind = 4;
+  return launch_x<C, C, X_FIRST>(op, (C*)op->t, x, y, B, nullptr, nullptr, 0.0, has_x, red_row(op, -1));
 }
 
 // Middle passes of one iteration plus the fused update/first pass of the next.
@@ -269,11 +317,16 @@ int iteration(usp_op op, C* x, const C* y, const C* B, double alpha) {
   C* t = (C*)op->t;
   const SymArgs sa = sym_args(op, true);
   int rc;
+  op->kind = 1;
   if (op->d.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa))) return rc;
+  op->kind = 2;
   if ((rc = launch_s<C, S_SYM>(op, t, 0, sa))) return rc;
+  op->kind = 3;
   if (op->d.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa))) return rc;
-  return launch_x<C, C, X_FUSED>(op, t, x, y, B, nullptr, nullptr, alpha, 1,
-                                 red_args(op, op->hist, op->slots, kHist));
+  op->kind = 0;
+  if ((rc = launch_x<C, C, X_FUSED>(op, t, x, y, B, nullptr, nullptr, alpha, 1, red_row(op, op->pending)))) return rc;
+  if (++op->pending == kRows) return finalize_hist(op);
+  return 0;
 }
 
 // FP64 true residual of x (storage Cx); ||r||^2 -> scal[0].  d: correction added
@@ -283,21 +336,27 @@ int residual_passes(usp_op op, Cx* x, const Cx* y, const Cx* B, const float2* d,
   double2* S = op->S;
   const SymArgs sa = sym_args(op, false);
   int rc;
-  if ((rc = launch_x<double2, Cx, X_RFWD>(op, S, x, y, B, d, nullptr, 0.0, 0, red_args(op, nullptr, nullptr, 0))))
-    return rc;
+  op->kind = 5;
+  if ((rc = launch_x<double2, Cx, X_RFWD>(op, S, x, y, B, d, nullptr, 0.0, 0, red_row(op, -1)))) return rc;
+  op->kind = 6;
   if (op->d.ndim == 3 && (rc = launch_s<double2, S_FWD>(op, S, 1, sa))) return rc;
+  op->kind = 7;
   if ((rc = launch_s<double2, S_SYMA>(op, S, 0, sa))) return rc;
+  op->kind = 8;
   if (op->d.ndim == 3 && (rc = launch_s<double2, S_INV>(op, S, 1, sa))) return rc;
-  return launch_x<double2, Cx, X_RINV>(op, S, x, y, B, nullptr, r32, 0.0, 0, red_args(op, op->scal, nullptr, 0));
+  op->kind = 9;
+  if ((rc = launch_x<double2, Cx, X_RINV>(op, S, x, y, B, nullptr, r32, 0.0, 0, red_row(op, kRows)))) return rc;
+  op->kind = USP_PASS_REDUCE;
+  return sum_rows(op, kRows, 1, x_blocks<double2>(op), op->scal, 0, 1);
 }
 
 template <class C>
 int norm2(usp_op op, const C* z, double* out) {
   const long n = op->d.N;
   int blocks = (int)std::min<long>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL((k_norm2<C>), dim3(blocks), dim3(256), 0, op->st, z, n, op->partials, op->counters, out);
+  hipLaunchKernelGGL((k_norm2<C>), dim3(blocks), dim3(256), 0, op->st, z, n, op->partials + (long)(kRows + 1) * op->pitch);
   LAUNCHCHK("k_norm2");
-  return 0;
+  return sum_rows(op, kRows + 1, 1, blocks, out, 0, 1);
 }
 
 Sym1D sym1d(usp_op op) {
@@ -372,7 +431,7 @@ int solve_plain(usp_op op, const C* y, C* x, int x_is_guess, double alpha, doubl
   int rc;
   const C* B = (const C*)op->B;
   if ((rc = norm2(op, y, op->scal + 1))) return rc;
-  HIPCHK(hipMemsetAsync(op->slots, 0, sizeof(int), op->st));
+  op->pending = op->pending_first = 0;
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * op->d.N, op->st));
   if ((rc = first_pass<C>(op, x, y, B, x_is_guess))) return rc;
   std::vector<double> buf;
@@ -383,6 +442,7 @@ int solve_plain(usp_op op, const C* y, C* x, int x_is_guess, double alpha, doubl
     ++it;
     const bool chk = check_residual && (it % check_every == 0 || it == maxit);
     if (chk) {
+      if ((rc = finalize_hist(op))) return rc;
       if ((rc = residual_passes<C>(op, x, y, B, nullptr, nullptr))) return rc;
       HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
       if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
@@ -394,10 +454,12 @@ int solve_plain(usp_op op, const C* y, C* x, int x_is_guess, double alpha, doubl
       if (mon.diverged) { status = USP_DIVERGED; break; }
       if (stag) { status = USP_STAGNATED; break; }
     } else if (it - pulled >= kHist / 2) {
+      if ((rc = finalize_hist(op))) return rc;
       if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
       pulled = it;
     }
   }
+  if ((rc = finalize_hist(op))) return rc;
   if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
   HIPCHK(hipStreamSynchronize(op->st));
   if (iters_out) *iters_out = it;
@@ -411,7 +473,7 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
   int rc;
   const double2* B = (const double2*)op->B;
   if ((rc = norm2(op, y, op->scal + 1))) return rc;
-  HIPCHK(hipMemsetAsync(op->slots, 0, sizeof(int), op->st));
+  op->pending = op->pending_first = 0;
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * op->d.N, op->st));
   std::vector<double> buf;
   int it = 0, pulled = 0, status = USP_MAXIT;
@@ -419,6 +481,7 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
   const float2* d = nullptr;
   while (true) {
     // r = y - A (x + d) in FP64; x <- x + d; r32 = complex64(r)
+    if ((rc = finalize_hist(op))) return rc;
     if ((rc = residual_passes<double2>(op, x, y, B, d, op->r32))) return rc;
     HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
     if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
@@ -564,8 +627,7 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
     }
   }
   op->partials = (double*)(w + lay.partials);
-  op->counters = (unsigned*)(w + lay.counters);
-  op->slots = (int*)(w + lay.slots);
+  op->pitch = lay.nblk;
   op->hist = (double*)(w + lay.hist);
   op->scal = (double*)(w + lay.scal);
   op->hist_true = (double*)(w + lay.hist_true);
@@ -627,9 +689,6 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
         hipStreamSynchronize(op->st) != hipSuccess)
       return cleanup(fail(USP_ERR_HIP, "table upload failed"));
   }
-  if (hipMemsetAsync(op->counters, 0, 64 * sizeof(unsigned), op->st) != hipSuccess ||
-      hipMemsetAsync(op->slots, 0, 64 * sizeof(int), op->st) != hipSuccess)
-    return cleanup(fail(USP_ERR_HIP, "workspace init failed"));
   if (op->refine) {
     hipLaunchKernelGGL(k_to_c64, dim3(1024), dim3(256), 0, op->st, (const double2*)B_dev, op->B32, d.N);
     if (hipGetLastError() != hipSuccess) return cleanup(fail(USP_ERR_HIP, "k_to_c64 launch failed"));
@@ -737,6 +796,87 @@ int usp_residual(usp_op op, const void* y_dev, const void* x_dev, double* rel_ou
   if (rel_out) *rel_out = std::sqrt(host[0] / host[1]);
   if (rnorm_out) *rnorm_out = std::sqrt(host[0]);
   if (ynorm_out) *ynorm_out = std::sqrt(host[1]);
+  return 0;
+}
+
+int usp_profile(usp_op op, const void* y_dev, void* x_dev, double alpha, int K, double* pass_ms, double* iter_ms) {
+  if (!op || !y_dev || !x_dev || !pass_ms || K < 1) return fail(USP_ERR_INVALID, "invalid argument");
+  if (op->d.ndim < 2) return fail(USP_ERR_INVALID, "usp_profile is for 2-D / 3-D grids");
+  std::vector<hipEvent_t> ev[USP_NPASS];
+  op->prof = ev;
+  int rc = 0;
+  auto run = [&]() -> int {
+    int r;
+    if (op->refine) {
+      if ((r = norm2(op, (const double2*)y_dev, op->scal + 1))) return r;
+      if ((r = residual_passes<double2>(op, (double2*)x_dev, (const double2*)y_dev, (const double2*)op->B, nullptr,
+                                        op->r32)))
+        return r;
+      HIPCHK(hipMemsetAsync(op->d32, 0, sizeof(float2) * op->d.N, op->st));
+      if ((r = first_pass<float2>(op, op->d32, op->r32, op->B32, 0))) return r;
+      for (int j = 0; j < K; ++j)
+        if ((r = iteration<float2>(op, op->d32, op->r32, op->B32, alpha))) return r;
+    } else if (op->dtype == USP_C64) {
+      const float2 *y = (const float2*)y_dev, *B = (const float2*)op->B;
+      float2* x = (float2*)x_dev;
+      if ((r = norm2(op, y, op->scal + 1))) return r;
+      HIPCHK(hipMemsetAsync(x, 0, sizeof(float2) * op->d.N, op->st));
+      if ((r = first_pass<float2>(op, x, y, B, 0))) return r;
+      for (int j = 0; j < K; ++j)
+        if ((r = iteration<float2>(op, x, y, B, alpha))) return r;
+      if ((r = residual_passes<float2>(op, x, y, B, nullptr, nullptr))) return r;
+    } else {
+      const double2 *y = (const double2*)y_dev, *B = (const double2*)op->B;
+      double2* x = (double2*)x_dev;
+      if ((r = norm2(op, y, op->scal + 1))) return r;
+      HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * op->d.N, op->st));
+      if ((r = first_pass<double2>(op, x, y, B, 0))) return r;
+      for (int j = 0; j < K; ++j)
+        if ((r = iteration<double2>(op, x, y, B, alpha))) return r;
+      if ((r = residual_passes<double2>(op, x, y, B, nullptr, nullptr))) return r;
+    }
+    return 0;
+  };
+  op->pending = op->pending_first = 0;
+  rc = run();
+  if (!rc) rc = finalize_hist(op);
+  op->prof = nullptr;
+  if (hipStreamSynchronize(op->st) != hipSuccess && !rc) rc = fail(USP_ERR_HIP, "synchronize failed");
+  for (int k = 0; k < USP_NPASS; ++k) {
+    double tot = 0.0;
+    const size_t n = ev[k].size() / 2;
+    for (size_t i = 0; i < n; ++i) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[k][2 * i], ev[k][2 * i + 1]);
+      tot += ms;
+    }
+    pass_ms[k] = n ? tot / n : 0.0;
+    for (hipEvent_t e : ev[k]) hipEventDestroy(e);
+  }
+  if (rc) return rc;
+  if (iter_ms) {
+    // whole iterations, no per-pass events
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int r = 0;
+    HIPCHK(hipEventRecord(e0, op->st));
+    for (int j = 0; j < K && !r; ++j) {
+      if (op->refine) r = iteration<float2>(op, op->d32, op->r32, op->B32, alpha);
+      else if (op->dtype == USP_C64)
+        r = iteration<float2>(op, (float2*)x_dev, (const float2*)y_dev, (const float2*)op->B, alpha);
+      else
+        r = iteration<double2>(op, (double2*)x_dev, (const double2*)y_dev, (const double2*)op->B, alpha);
+    }
+    HIPCHK(hipEventRecord(e1, op->st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (r) return r;
+    *iter_ms = ms / K;
+  }
   return 0;
 }
 

@@ -236,39 +236,13 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return s;
 }
 
-// Grid-level deterministic sum: each block stores its partial; the last block
-// to finish adds the partials in block order and writes the total to
-// out[(*slot) % nslots] (slot NULL: out[0]), advancing *slot, and re-arms the
-// arrival counter for the next launch.
-__device__ __forceinline__ void grid_sum_commit(double v, double* scratch, double* partials, unsigned* counter,
-                                                double* out, int* slot, int nslots) {
-  __shared__ int is_last;
+// Per-block partial of a grid reduction: the block's sum goes to row[block].
+// Rows are summed in block order by k_sum_rows in a later launch, so the result
+// is deterministic and no cross-block fence or atomic is needed (a device-scope
+// fence writes back the whole L2 on this chip).
+__device__ __forceinline__ void block_partial(double v, double* scratch, double* row) {
   const double s = block_sum(v, scratch);
-  const int nblocks = gridDim.x * gridDim.y * gridDim.z;
-  const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  if (threadIdx.x == 0) {
-    partials[bid] = s;
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = (prev == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (is_last) {
-    __threadfence();
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < nblocks; i += blockDim.x)
-      acc += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double tot = block_sum(acc, scratch);
-    if (threadIdx.x == 0) {
-      int k = 0;
-      if (slot) {
-        k = *slot;
-        *slot = k + 1;
-      }
-      out[nslots > 0 ? (k % nslots) : 0] = tot;
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
+  if (row && threadIdx.x == 0) row[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
 }
 
 }  // namespace usp

@@ -26,11 +26,7 @@ enum XMode { X_FIRST = 0, X_FUSED = 1, X_RFWD = 2, X_RINV = 3 };
 enum SMode { S_FWD = 0, S_INV = 1, S_SYM = 2, S_SYMA = 3 };
 
 struct RedArgs {
-  double* partials;
-  unsigned* counter;
-  double* out;
-  int* slot;
-  int nslots;
+  double* row;  // per-block partial sums of this launch (NULL: none)
 };
 
 template <class C> constexpr int x_threads() { return sizeof(C) == 8 ? 256 : 128; }
@@ -108,7 +104,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
-    grid_sum_commit(acc, scratch, red.partials, red.counter, red.out, red.slot, red.nslots);
+    block_partial(acc, scratch, red.row);
     return;
   }
 
@@ -148,7 +144,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
         if (r32) r32[p] = cvt<float2>(r);
       }
     }
-    grid_sum_commit(acc, scratch, red.partials, red.counter, red.out, red.slot, red.nslots);
+    block_partial(acc, scratch, red.row);
     return;
   }
 }

@@ -22,15 +22,26 @@ __global__ void k_canonical_fields(const double2* __restrict__ q, const double2*
   }
 }
 
-// sum |z|^2 (deterministic grid reduction into out[0])
+// per-block partial sums of |z|^2 into row[block]
 template <class C>
-__global__ void __launch_bounds__(256) k_norm2(const C* __restrict__ z, long n, double* partials, unsigned* counter,
-                                               double* out) {
+__global__ void __launch_bounds__(256) k_norm2(const C* __restrict__ z, long n, double* row) {
   __shared__ double scratch[64];
   double acc = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     acc += cabs2(z[i]);
-  grid_sum_commit(acc, scratch, partials, counter, out, nullptr, 0);
+  block_partial(acc, scratch, row);
+}
+
+// Block r adds row r of `part` (ncols partials, row pitch `pitch`) in a fixed
+// order and writes out[(first + r) % nmod].
+__global__ void __launch_bounds__(256) k_sum_rows(const double* __restrict__ part, long pitch, int ncols,
+                                                  double* __restrict__ out, int first, int nmod) {
+  __shared__ double scratch[64];
+  const double* row = part + (long)blockIdx.x * pitch;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < ncols; i += blockDim.x) acc += row[i];
+  const double s = block_sum(acc, scratch);
+  if (threadIdx.x == 0) out[(first + (int)blockIdx.x) % nmod] = s;
 }
 
 // per-block max |1 - B|  ->  partials[block]

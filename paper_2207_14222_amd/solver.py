@@ -214,6 +214,14 @@ class Operator:
         L.check(L.lib().usp_iterate(self.handle, _ptr(y), _ptr(x), int(guess), float(alpha), int(K), _dp(hp), K))
         return x, hp[:K].copy()
 
+    def profile(self, y, x, alpha=0.8, K=20):
+        """Per-pass average launch time (ms) and per-iteration time (ms) via usp_profile."""
+        pm = np.zeros(L.USP_NPASS)
+        it = np.zeros(1)
+        L.check(L.lib().usp_profile(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), float(alpha), int(K),
+                                    _dp(pm), _dp(it)))
+        return dict(zip(L.PASS_NAMES, pm.tolist())), float(it[0])
+
     def residual(self, y, x):
         """(||y - A x||/||y||, ||y - A x||, ||y||) in FP64."""
         rel, rn, yn = np.zeros(1), np.zeros(1), np.zeros(1)
