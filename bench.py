@@ -30,6 +30,32 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "time to ‖r‖/‖y‖<1e-6 + GB/s/iter, 256³ Helmholtz; plain vs learned-x0 vs batched"
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "x_fused_helmholtz3d_256_traffic.md")
+
+
+def recorded_traffic(plan, shape):
+    """HBM bytes per x_fused launch from the committed rocprofv3 counter summary,
+    or None if the kernel sources or the plan differ from those it was taken with."""
+    import hashlib
+    if shape != (256, 256, 256) or not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "plan", "sources_sha256_16"):
+            k, v = line.split(":", 1)
+            kv[k] = v.strip()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2207_14222_amd", "csrc")
+    src = open(os.path.join(csrc, "fft.hpp"), "rb").read() + open(os.path.join(csrc, "passes.hpp"), "rb").read()
+    if hashlib.sha256(src).hexdigest()[:16] != kv.get("sources_sha256_16"):
+        return None
+    rp = [int(v) for v in kv.get("plan", "").split(",")]
+    if len(rp) != 4 or (rp[0], rp[3]) != (plan["x_prefetch"], plan["x_stream"]):
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -67,6 +93,10 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain complex128/complex64 reference solves")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
+    ap.add_argument("--plan", default=None, help="force a launch plan 'x_prefetch,w_mid,w_sym,x_stream' (no tuning)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -95,9 +125,34 @@ def main():
     def refined_solve():
         return op_ref.solve(y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every)
 
+    # measured device-to-device copy bandwidth (read + write bytes), the
+    # practical streaming ceiling beside the 8 TB/s peak
+    a = torch.empty(1 << 27, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ncopy = 5 if args.copy_probe else 4
+    e0.record()
+    for _ in range(ncopy):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * a.numel() * 8 * ncopy / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    log(f"copy: {ncopy} x 1 GiB device-to-device, {copy_gbs:.0f} GB/s (read + write)")
     for w in range(args.warmup):
         r = refined_solve()
         log(f"warmup {w + 1}/{args.warmup}: {r.iterations} iterations, status {r.status_name}")
+    plan = op_ref.get_plan()
+    if args.plan:
+        op_ref.set_plan(*[int(v) for v in args.plan.split(",")])
+        plan = op_ref.get_plan()
+        log(f"plan {plan}")
+    elif not args.no_tune:
+        r = refined_solve()   # workspace holds a valid inner problem for tuning
+        plan = op_ref.autotune(y, x, alpha=args.alpha, reps=5)
+        log(f"autotuned plan {plan}")
     times = []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
@@ -128,8 +183,9 @@ def main():
     per_iter_kernels = ["x_fused", "sym"] + (["m_fwd", "m_inv"] if nd == 3 else [])
     dom = max(per_iter_kernels, key=lambda k: pass_ms[k])
     ach = pass_bytes[dom] / (pass_ms[dom] * 1e-3) / 1e9
+    traffic = recorded_traffic(plan, shape) if dom == "x_fused" else None
     roofline = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "avg_launch_us": round(pass_ms[dom] * 1e3, 2),
                 "bytes_per_launch": pass_bytes[dom]}
     gbs_iter = iter_bytes / (iter_ms * 1e-3) / 1e9
@@ -184,8 +240,10 @@ def main():
                    "helmholtz3d_spheres_" + "x".join(map(str, shape)),
                    "grid": list(shape), "alpha": args.alpha, "tol": args.tol,
                    "refine_every": args.refine_every, "iterations": iters, "converged": converged,
+                   "plan": plan,
                    "mode": "complex64 iterations + FP64 residual refinement"},
         "GB/s_per_iter": round(gbs_iter, 1),
+        "copy_GB/s": round(copy_gbs, 1),
         "ms_per_iter": round(iter_ms, 4),
         "iter_model_bytes": iter_bytes,
         "roofline": roofline,

@@ -96,6 +96,22 @@ typedef struct {
 
 typedef struct usp_op_s* usp_op;
 
+/* Launch plan of the complex64 iteration passes (2-D / 3-D grids).  Every plan
+ * computes bit-identical results; only speed differs.
+ *   x_prefetch  1: the fused contiguous-axis pass loads x, B, y before its
+ *               inverse FFT (more registers, more loads in flight)
+ *   x_stream    1: the fused pass reads x, B, y and writes x with non-temporal
+ *               (streaming) accesses so the temporary spectrum stays cached
+ *   w_mid       column-tile width (elements, 4/8/16/32; 0 = default) of the
+ *               middle-axis passes (3-D)
+ *   w_sym       column-tile width of the symbol pass (first axis) */
+typedef struct {
+  int x_prefetch;
+  int w_mid;
+  int w_sym;
+  int x_stream;
+} usp_plan;
+
 /* Workspace size for an operator.  dtype: USP_C64 or USP_C128; flags: 0 or
  * USP_FLAG_REFINE (requires USP_C128).  Errors: INVALID, UNSUPPORTED_SHAPE. */
 int usp_workspace_bytes(const usp_symbol* L, int dtype, int flags, size_t* bytes);
@@ -167,6 +183,18 @@ int usp_residual(usp_op op, const void* y_dev, const void* x_dev, double* rel_ou
 #define USP_PASS_R_INV 9     /* FP64 residual: inverse FFT, r = y - A x, ||r||^2 */
 #define USP_PASS_REDUCE 10   /* ordered sum of per-block partial norms */
 int usp_profile(usp_op op, const void* y_dev, void* x_dev, double alpha, int K, double* pass_ms, double* iter_ms);
+
+/* Read / set the launch plan of a handle (see usp_plan).  Invalid widths:
+ * USP_ERR_INVALID; widths that do not fit an axis fall back to the largest
+ * valid smaller width at launch. */
+int usp_get_plan(usp_op op, usp_plan* out);
+int usp_set_plan(usp_op op, const usp_plan* plan);
+
+/* Autotuner: times `reps` iterations (best of two) for every candidate plan on
+ * y_dev / x_dev (x_dev overwritten; in refined mode the workspace copies are
+ * used) and keeps the fastest in the handle; best_out may be NULL.  Results of
+ * all candidates are identical, so tuning never changes a solution. */
+int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int reps, usp_plan* best_out);
 
 /* Destroy a handle (frees host memory only). */
 int usp_destroy(usp_op op);

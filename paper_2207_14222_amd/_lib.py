@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "
 
 EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iterate", "usp_residual",
            "usp_destroy", "usp_last_error", "usp_smallest_circle", "usp_canonical_fields",
-           "usp_canonical_helmholtz", "usp_canonical_diffusion", "usp_profile"]
+           "usp_canonical_helmholtz", "usp_canonical_diffusion", "usp_profile", "usp_get_plan", "usp_set_plan",
+           "usp_autotune"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -33,6 +34,10 @@ class usp_symbol(ct.Structure):
     _fields_ = [("ndim", ct.c_int), ("shape", ct.c_int * 3), ("spacing", ct.c_double * 3),
                 ("s", ct.c_double * 2), ("a0", ct.c_double * 2), ("a1", ct.c_double * 2),
                 ("a2", ct.c_double * 2), ("nyquist_zero", ct.c_int)]
+
+
+class usp_plan(ct.Structure):
+    _fields_ = [("x_prefetch", ct.c_int), ("w_mid", ct.c_int), ("w_sym", ct.c_int), ("x_stream", ct.c_int)]
 
 
 class usp_gather(ct.Structure):
@@ -73,6 +78,10 @@ def lib():
     L.usp_canonical_helmholtz.argtypes = [DP, Z, I, DP, D, SP, SP, DP, DP]
     L.usp_canonical_diffusion.argtypes = [DP, Z, D, D, D, SP, SP, DP, DP]
     L.usp_profile.argtypes = [P, P, P, D, I, DP, DP]
+    PP = ct.POINTER(usp_plan)
+    L.usp_get_plan.argtypes = [P, PP]
+    L.usp_set_plan.argtypes = [P, PP]
+    L.usp_autotune.argtypes = [P, P, P, D, I, PP]
     for name in EXPORTS:
         if name != "usp_last_error":
             getattr(L, name).restype = ct.c_int

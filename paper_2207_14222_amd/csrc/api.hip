@@ -72,7 +72,6 @@ struct Layout {
   size_t t = 0, S = 0, B32 = 0, r32 = 0, d32 = 0;
   size_t partials = 0, hist = 0, scal = 0, hist_true = 0, info = 0;
   size_t twf[11] = {0}, twd[11] = {0};
-  size_t q0 = 0, q1 = 0, q2 = 0, qzero = 0;
   size_t total = 0;
   long nblk = 0;
 };
@@ -138,10 +137,6 @@ int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, Dims* di
       lay->twd[l] = take(sizeof(double2) * n);
     }
   }
-  lay->q0 = take(sizeof(double) * dims->n0);
-  lay->q1 = take(sizeof(double) * dims->n1);
-  lay->q2 = take(sizeof(double) * dims->n2);
-  lay->qzero = take(sizeof(double) * 8);
   lay->total = off;
   return 0;
 }
@@ -173,9 +168,9 @@ struct usp_op_s {
   Solve1DInfo* info = nullptr;
   float2* twf[11] = {nullptr};
   double2* twd[11] = {nullptr};
-  double *q0 = nullptr, *q1 = nullptr, *q2 = nullptr, *qzero = nullptr;
   // symbol multiplier constants
   double sa0[2], sa1[2], sa2[2];
+  usp_plan plan{};
   // per-pass event timing (usp_profile)
   std::vector<hipEvent_t>* prof = nullptr;  // array of USP_NPASS vectors of (start, stop) events
   int kind = 0;
@@ -241,6 +236,7 @@ int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d,
              int has_x, RedArgs red) {
   const Dims& D = op->d;
   const int nlines = D.n0 * D.n1;
+  const int fl = (MODE == X_FUSED) ? ((op->plan.x_prefetch ? 1 : 0) | (op->plan.x_stream ? 2 : 0)) : 0;
   bool ok = with_n(D.n2, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     constexpr int E = PassPlan<N>::E, T = N / E;
@@ -249,8 +245,17 @@ int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d,
     const int blocks = (nlines + LPB - 1) / LPB;
     if (MODE == X_FUSED) op->xblocks = blocks;
     prof_mark(op);
-    hipLaunchKernelGGL((k_xpass<Cc, Cx, N, MODE>), dim3(blocks), dim3(TPB), 0, op->st, t, x, y, B, d, r32,
-                       tw_for<Cc>(op, N), alpha, nlines, has_x, red);
+    auto go = [&](auto FC) {
+      constexpr int F = decltype(FC)::value;
+      hipLaunchKernelGGL((k_xpass<Cc, Cx, N, MODE, F>), dim3(blocks), dim3(TPB), 0, op->st, t, x, y, B, d, r32,
+                         tw_for<Cc>(op, N), alpha, nlines, has_x, red);
+    };
+    switch (fl) {
+      case 1: go(std::integral_constant<int, 1>{}); break;
+      case 2: go(std::integral_constant<int, 2>{}); break;
+      case 3: go(std::integral_constant<int, 3>{}); break;
+      default: go(std::integral_constant<int, 0>{}); break;
+    }
     prof_mark(op);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
@@ -258,44 +263,66 @@ int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d,
   return 0;
 }
 
-template <class C, int N> constexpr int pick_w() {
-  if constexpr (sizeof(C) == 8) return N >= 1024 ? 8 : 16;
-  else return N >= 1024 ? 4 : 8;
+template <class C> int default_w(int N) {
+  if (sizeof(C) == 8) return N >= 1024 ? 8 : 16;
+  return N >= 1024 ? 4 : 8;
 }
 
-// strided pass along axis 0 (ax = 0) or axis 1 (ax = 1, 3-D only)
+template <class C> bool width_ok(int N, int W) {
+  bool ok = false;
+  with_n(N, [&](auto NC) {
+    constexpr int Nn = decltype(NC)::value;
+    ok = s_width_ok<C>(Nn, W, PassPlan<Nn>::E);
+  });
+  return ok && (W == 4 || W == 8 || W == 16 || W == 32);
+}
+
+// strided pass along axis 0 (ax = 0) or axis 1 (ax = 1, 3-D only) with column
+// tiles of W elements (W <= the axis stride S; the largest valid width <= W is used)
 template <class C, int MODE>
-int launch_s(usp_op op, C* data, int ax, const SymArgs& sym) {
+int launch_s(usp_op op, C* data, int ax, const SymArgs& sym, int W) {
   const Dims& D = op->d;
   const int n = ax == 0 ? D.n0 : D.n1;
   const long S = ax == 0 ? (long)D.n1 * D.n2 : (long)D.n2;
   const int batch = ax == 0 ? 1 : D.n0;
+  if (W <= 0) W = default_w<C>(n);
+  while (W > 4 && (W > S || !width_ok<C>(n, W))) W >>= 1;
+  bool launched = false;
   bool ok = with_n(n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     constexpr int E = PassPlan<N>::E, T = N / E;
-    constexpr int Wd = pick_w<C, N>();
-    prof_mark(op);
-    if (S >= Wd) {
-      hipLaunchKernelGGL((k_spass<C, N, Wd, MODE>), dim3((unsigned)(S / Wd), batch), dim3(Wd * T), 0, op->st,
-                         data, tw_for<C>(op, N), S, sym);
-    } else {
-      constexpr int W8 = 8;
-      hipLaunchKernelGGL((k_spass<C, N, W8, MODE>), dim3((unsigned)(S / W8), batch), dim3(W8 * T), 0, op->st,
-                         data, tw_for<C>(op, N), S, sym);
+    auto go = [&](auto WC) {
+      constexpr int Wc = decltype(WC)::value;
+      if constexpr (s_width_ok<C>(N, Wc, E)) {
+        prof_mark(op);
+        hipLaunchKernelGGL((k_spass<C, N, Wc, MODE>), dim3((unsigned)(S / Wc), batch), dim3(Wc * T), 0, op->st,
+                           data, tw_for<C>(op, N), S, sym);
+        prof_mark(op);
+        launched = true;
+      }
+    };
+    switch (W) {
+      case 4: go(std::integral_constant<int, 4>{}); break;
+      case 8: go(std::integral_constant<int, 8>{}); break;
+      case 16: go(std::integral_constant<int, 16>{}); break;
+      case 32: go(std::integral_constant<int, 32>{}); break;
+      default: break;
     }
-    prof_mark(op);
   });
-  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "strided axis length");
+  if (!ok || !launched) return fail(USP_ERR_UNSUPPORTED_SHAPE, "strided axis length / tile width");
   LAUNCHCHK("k_spass");
   return 0;
 }
 
 SymArgs sym_args(usp_op op, bool plus_one) {
   SymArgs a;
-  a.qa = op->q0;
-  a.qm = op->d.ndim == 3 ? op->q1 : op->qzero;
-  a.qx = op->q2;
-  a.log2_n2 = ilog2(op->d.n2);
+  const Dims& D = op->d;
+  auto sc = [](int n, double h) { return n > 1 ? std::pow(2.0 * M_PI / (n * h), 2) : 0.0; };
+  a.sa = sc(D.n0, op->sym.spacing[0]);
+  a.sm = D.ndim == 3 ? sc(D.n1, op->sym.spacing[1]) : 0.0;
+  a.sx = sc(D.n2, op->sym.spacing[D.ndim - 1]);
+  a.n1 = D.n1;
+  a.log2_n2 = ilog2(D.n2);
   a.c0r = op->sa0[0] + (plus_one ? 1.0 : 0.0);
   a.c0i = op->sa0[1];
   a.c2r = op->sa2[0];
@@ -318,11 +345,12 @@ int iteration(usp_op op, C* x, const C* y, const C* B, double alpha) {
   const SymArgs sa = sym_args(op, true);
   int rc;
   op->kind = 1;
-  if (op->d.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa))) return rc;
+  const int wm = sizeof(C) == 8 ? op->plan.w_mid : 0, ws = sizeof(C) == 8 ? op->plan.w_sym : 0;
+  if (op->d.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa, wm))) return rc;
   op->kind = 2;
-  if ((rc = launch_s<C, S_SYM>(op, t, 0, sa))) return rc;
+  if ((rc = launch_s<C, S_SYM>(op, t, 0, sa, ws))) return rc;
   op->kind = 3;
-  if (op->d.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa))) return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa, wm))) return rc;
   op->kind = 0;
   if ((rc = launch_x<C, C, X_FUSED>(op, t, x, y, B, nullptr, nullptr, alpha, 1, red_row(op, op->pending)))) return rc;
   if (++op->pending == kRows) return finalize_hist(op);
@@ -339,11 +367,11 @@ int residual_passes(usp_op op, Cx* x, const Cx* y, const Cx* B, const float2* d,
   op->kind = 5;
   if ((rc = launch_x<double2, Cx, X_RFWD>(op, S, x, y, B, d, nullptr, 0.0, 0, red_row(op, -1)))) return rc;
   op->kind = 6;
-  if (op->d.ndim == 3 && (rc = launch_s<double2, S_FWD>(op, S, 1, sa))) return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<double2, S_FWD>(op, S, 1, sa, 0))) return rc;
   op->kind = 7;
-  if ((rc = launch_s<double2, S_SYMA>(op, S, 0, sa))) return rc;
+  if ((rc = launch_s<double2, S_SYMA>(op, S, 0, sa, 0))) return rc;
   op->kind = 8;
-  if (op->d.ndim == 3 && (rc = launch_s<double2, S_INV>(op, S, 1, sa))) return rc;
+  if (op->d.ndim == 3 && (rc = launch_s<double2, S_INV>(op, S, 1, sa, 0))) return rc;
   op->kind = 9;
   if ((rc = launch_x<double2, Cx, X_RINV>(op, S, x, y, B, nullptr, r32, 0.0, 0, red_row(op, kRows)))) return rc;
   op->kind = USP_PASS_REDUCE;
@@ -632,10 +660,6 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
   op->scal = (double*)(w + lay.scal);
   op->hist_true = (double*)(w + lay.hist_true);
   op->info = (Solve1DInfo*)(w + lay.info);
-  op->q0 = (double*)(w + lay.q0);
-  op->q1 = (double*)(w + lay.q1);
-  op->q2 = (double*)(w + lay.q2);
-  op->qzero = (double*)(w + lay.qzero);
   cmulh(L->s, L->a0, op->sa0);
   cmulh(L->s, L->a1, op->sa1);
   cmulh(L->s, L->a2, op->sa2);
@@ -664,30 +688,6 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
         hipMemcpyAsync(op->twd[l], td.data(), n * sizeof(double2), hipMemcpyHostToDevice, op->st) != hipSuccess ||
         hipStreamSynchronize(op->st) != hipSuccess)
       return cleanup(fail(USP_ERR_HIP, "twiddle upload failed"));
-  }
-  // (p_axis)^2 tables: p_k = 2 pi fftfreq(n, h)
-  {
-    const int ns[3] = {d.n0, d.n1, d.n2};
-    double* dst[3] = {op->q0, op->q1, op->q2};
-    // spacing per internal axis
-    double hs[3];
-    if (d.ndim == 1) { hs[0] = hs[1] = 1.0; hs[2] = L->spacing[0]; }
-    else if (d.ndim == 2) { hs[0] = L->spacing[0]; hs[1] = 1.0; hs[2] = L->spacing[1]; }
-    else { hs[0] = L->spacing[0]; hs[1] = L->spacing[1]; hs[2] = L->spacing[2]; }
-    for (int a = 0; a < 3; ++a) {
-      std::vector<double> q(ns[a]);
-      for (int k = 0; k < ns[a]; ++k) {
-        const int kk = (k < (ns[a] + 1) / 2) ? k : k - ns[a];
-        const double p = (ns[a] == 1) ? 0.0 : 2.0 * M_PI * kk / (ns[a] * hs[a]);
-        q[k] = p * p;
-      }
-      if (hipMemcpyAsync(dst[a], q.data(), ns[a] * sizeof(double), hipMemcpyHostToDevice, op->st) != hipSuccess)
-        return cleanup(fail(USP_ERR_HIP, "table upload failed"));
-    }
-    std::vector<double> z(8, 0.0);
-    if (hipMemcpyAsync(op->qzero, z.data(), 8 * sizeof(double), hipMemcpyHostToDevice, op->st) != hipSuccess ||
-        hipStreamSynchronize(op->st) != hipSuccess)
-      return cleanup(fail(USP_ERR_HIP, "table upload failed"));
   }
   if (op->refine) {
     hipLaunchKernelGGL(k_to_c64, dim3(1024), dim3(256), 0, op->st, (const double2*)B_dev, op->B32, d.N);
@@ -877,6 +877,86 @@ int usp_profile(usp_op op, const void* y_dev, void* x_dev, double alpha, int K, 
     if (r) return r;
     *iter_ms = ms / K;
   }
+  return 0;
+}
+
+int usp_get_plan(usp_op op, usp_plan* out) {
+  if (!op || !out) return fail(USP_ERR_INVALID, "NULL argument");
+  *out = op->plan;
+  return 0;
+}
+
+int usp_set_plan(usp_op op, const usp_plan* plan) {
+  if (!op || !plan) return fail(USP_ERR_INVALID, "NULL argument");
+  for (int w : {plan->w_mid, plan->w_sym})
+    if (!(w == 0 || w == 4 || w == 8 || w == 16 || w == 32)) return fail(USP_ERR_INVALID, "tile width must be 0, 4, 8, 16 or 32");
+  op->plan = *plan;
+  return 0;
+}
+
+int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int reps, usp_plan* best_out) {
+  if (!op || !y_dev || !x_dev || reps < 1) return fail(USP_ERR_INVALID, "invalid argument");
+  if (op->d.ndim < 2) {
+    if (best_out) *best_out = op->plan;
+    return 0;
+  }
+  const bool c64 = op->refine || op->dtype == USP_C64;
+  const int ws_c64[] = {8, 16, 32}, ws_c128[] = {4, 8, 16};
+  const int* ws = c64 ? ws_c64 : ws_c128;
+  std::vector<usp_plan> cands;
+  for (int fl = 0; fl < 4; ++fl)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        usp_plan p{};
+        p.x_prefetch = fl & 1;
+        p.x_stream = (fl >> 1) & 1;
+        p.w_mid = op->d.ndim == 3 ? ws[a] : 0;
+        p.w_sym = ws[b];
+        if (op->d.ndim == 2 && a > 0) continue;
+        if ((p.w_mid && !(c64 ? width_ok<float2>(op->d.n1, p.w_mid) : width_ok<double2>(op->d.n1, p.w_mid))) ||
+            !(c64 ? width_ok<float2>(op->d.n0, p.w_sym) : width_ok<double2>(op->d.n0, p.w_sym)))
+          continue;
+        cands.push_back(p);
+      }
+  const usp_plan saved = op->plan;
+  double best_ms = INFINITY;
+  usp_plan best = saved;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (const usp_plan& p : cands) {
+    op->plan = p;
+    double ms_min = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+      int r = 0;
+      HIPCHK(hipEventRecord(e0, op->st));
+      for (int j = 0; j < reps && !r; ++j) {
+        if (op->refine) r = iteration<float2>(op, op->d32, op->r32, op->B32, alpha);
+        else if (op->dtype == USP_C64)
+          r = iteration<float2>(op, (float2*)x_dev, (const float2*)y_dev, (const float2*)op->B, alpha);
+        else
+          r = iteration<double2>(op, (double2*)x_dev, (const double2*)y_dev, (const double2*)op->B, alpha);
+      }
+      HIPCHK(hipEventRecord(e1, op->st));
+      HIPCHK(hipEventSynchronize(e1));
+      if (r) {
+        op->plan = saved;
+        return r;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, (double)ms);
+    }
+    if (ms_min < best_ms) {
+      best_ms = ms_min;
+      best = p;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  op->pending = op->pending_first = 0;
+  op->plan = best;
+  if (best_out) *best_out = best;
   return 0;
 }
 

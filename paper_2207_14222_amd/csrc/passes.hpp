@@ -31,9 +31,62 @@ struct RedArgs {
 
 template <class C> constexpr int x_threads() { return sizeof(C) == 8 ? 256 : 128; }
 
+// copy a length-N twiddle table into LDS (whole block participates)
+template <class C, int N>
+__device__ __forceinline__ void load_twiddles(C* tws, const C* __restrict__ tw) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tws[i] = tw[i];
+  __syncthreads();
+}
+
+// |p|^2 on the FFT grid from frequency indices: p_k = 2 pi (k or k - n)/(n h),
+// passed as per-axis scale (2 pi/(n h))^2.
+template <class R> __device__ __forceinline__ R fsq(int k, int n) {
+  const int f = (k < (n + 1) / 2) ? k : k - n;
+  return (R)(f * f);
+}
+
 // Contiguous-axis pass.  Cc: compute (and spectrum storage) type; Cx: storage
 // type of x, y, B.
-template <class Cc, class Cx, int N, int MODE>
+// streaming (non-temporal) global access for fields read or written once per
+// pass, so that they do not evict the temporary spectrum from the caches
+template <class C> __device__ __forceinline__ C ld_stream(const C* p) {
+  if constexpr (sizeof(C) == 8) {
+    const double d = __builtin_nontemporal_load(reinterpret_cast<const double*>(p));
+    C c;
+    __builtin_memcpy(&c, &d, 8);
+    return c;
+  } else {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v d = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+    C c;
+    __builtin_memcpy(&c, &d, 16);
+    return c;
+  }
+}
+template <class C> __device__ __forceinline__ void st_stream(C* p, C v) {
+  if constexpr (sizeof(C) == 8) {
+    double d;
+    __builtin_memcpy(&d, &v, 8);
+    __builtin_nontemporal_store(d, reinterpret_cast<double*>(p));
+  } else {
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    d2v d;
+    __builtin_memcpy(&d, &v, 16);
+    __builtin_nontemporal_store(d, reinterpret_cast<d2v*>(p));
+  }
+}
+template <bool NT, class C> __device__ __forceinline__ C ld(const C* p) {
+  if constexpr (NT) return ld_stream(p);
+  else return *p;
+}
+template <bool NT, class C> __device__ __forceinline__ void st(C* p, C v) {
+  if constexpr (NT) st_stream(p, v);
+  else *p = v;
+}
+
+// FL (fused pass only): bit 0 = load x, B, y before the inverse FFT;
+// bit 1 = stream x, B, y (non-temporal loads / store)
+template <class Cc, class Cx, int N, int MODE, int FL = 0>
 __global__ void __launch_bounds__(x_threads<Cc>())
 k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const Cx* __restrict__ B,
         const float2* __restrict__ d, float2* __restrict__ r32, const Cc* __restrict__ tw, double alpha,
@@ -45,9 +98,11 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
   constexpr int LPB = (TPB / T) > 0 ? (TPB / T) : 1;
   constexpr int PADN = LdsRow<Cc>::padded(N);
   __shared__ Cc lds[LPB * PADN];
+  __shared__ Cc tws[N];
   __shared__ double scratch[64];
 
   const int tid = threadIdx.x;
+  load_twiddles<Cc, N>(tws, tw);
   const int tt = tid % T, li = tid / T;
   const long line = (long)blockIdx.x * LPB + li;
   const bool active = (li < LPB) && (line < nlines);
@@ -67,7 +122,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
       }
       v[e] = val;
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tw, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
@@ -75,37 +130,53 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
     return;
   }
 
-  if (MODE == X_FUSED || MODE == X_RINV) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = active ? t[base + tt + T * e] : mk<Cc>(0.0, 0.0);
-    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tw, BlockSync{});
-  }
-
   if (MODE == X_FUSED) {
+    // PF: x, B, y are loaded before the inverse FFT so their latency overlaps
+    // it (more registers live across the FFT); otherwise after it.
+    constexpr bool PF = (FL & 1) != 0, NT = (FL & 2) != 0;
+    Cc xx[E], bb[E], yy[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const long p = base + tt + T * e;
+      v[e] = active ? t[p] : mk<Cc>(0.0, 0.0);
+      if (PF) {
+        xx[e] = active ? cvt<Cc>(ld<NT>(x + p)) : mk<Cc>(0.0, 0.0);
+        bb[e] = active ? cvt<Cc>(ld<NT>(B + p)) : mk<Cc>(0.0, 0.0);
+        yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
+      }
+    }
+    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    if (!PF) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const long p = base + tt + T * e;
+        xx[e] = active ? cvt<Cc>(ld<NT>(x + p)) : mk<Cc>(0.0, 0.0);
+        bb[e] = active ? cvt<Cc>(ld<NT>(B + p)) : mk<Cc>(0.0, 0.0);
+        yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
+      }
+    }
     const Rr a = (Rr)alpha;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      if (active) {
-        const long p = base + tt + T * e;
-        const Cc xx = cvt<Cc>(x[p]);
-        const Cc bb = cvt<Cc>(B[p]);
-        const Cc yy = cvt<Cc>(y[p]);
-        const Cc dl = cmul(bb, csub(v[e], xx));     // Delta = B (u - x)
-        const Cc xn = cadd(xx, cscale(dl, a));      // x + alpha Delta
-        acc += cabs2(dl);
-        x[p] = cvt<Cx>(xn);
-        v[e] = cadd(cmul(bb, xn), yy);              // next t = B x + y
-      } else {
-        v[e] = mk<Cc>(0.0, 0.0);
-      }
+      const Cc dl = cmul(bb[e], csub(v[e], xx[e]));     // Delta = B (u - x)
+      const Cc xn = cadd(xx[e], cscale(dl, a));         // x + alpha Delta
+      acc += cabs2(dl);
+      if (active) st<NT>(x + base + tt + T * e, cvt<Cx>(xn));
+      v[e] = cadd(cmul(bb[e], xn), yy[e]);              // next t = B x + y
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tw, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
     block_partial(acc, scratch, red.row);
     return;
+  }
+
+  if (MODE == X_RINV) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = active ? t[base + tt + T * e] : mk<Cc>(0.0, 0.0);
+    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
   }
 
   if (MODE == X_RFWD) {
@@ -122,7 +193,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
       }
       v[e] = val;
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tw, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
@@ -152,15 +223,17 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
 // Strided-axis pass over a tile of W adjacent columns.  Element (pos, col, b)
 // lives at b*N*S + pos*S + col.  blockIdx.x: column tile, blockIdx.y: batch.
 struct SymArgs {
-  const double* qa;  // (p_axis)^2 along the transformed axis, N entries
-  const double* qm;  // (p)^2 along n1 (3-D) or a single 0 (2-D)
-  const double* qx;  // (p)^2 along n2
-  int log2_n2;
+  double sa, sm, sx;          // (2 pi/(n h))^2 of the transformed axis, n1 (0 in 2-D), n2
+  int n1, log2_n2;            // n1 = 1 in 2-D
   double c0r, c0i, c2r, c2i;  // multiplier base: c0 + c2 |p|^2
   double scale;               // 1/Ntotal
 };
 
-template <class C> constexpr int s_lds_ok(int N, int W) { return N * (W + 1) * (int)sizeof(C) <= 150 * 1024; }
+// a column-tile width W is usable for length N if the tile and the twiddles fit
+// in LDS and the block has at most 1024 threads
+template <class C> constexpr bool s_width_ok(int N, int W, int E) {
+  return (N * (W + 1) + N) * (int)sizeof(C) <= 160 * 1024 && W * (N / E) <= 1024;
+}
 
 template <class C, int N, int W, int MODE>
 __global__ void __launch_bounds__(W * (N / PassPlan<N>::E))
@@ -169,6 +242,7 @@ k_spass(C* __restrict__ data, const C* __restrict__ tw, long S, SymArgs sym) {
   using PP = PassPlan<N>;
   constexpr int E = PP::E, T = N / E;
   __shared__ C lds[N * (W + 1)];
+  __shared__ C tws[N];
   const int tid = threadIdx.x;
   const int c = tid % W, tt = tid / W;
   const long col = (long)blockIdx.x * W + c;
@@ -177,25 +251,28 @@ k_spass(C* __restrict__ data, const C* __restrict__ tw, long S, SymArgs sym) {
   C v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = data[base + (long)(tt + T * e) * S];
+  load_twiddles<C, N>(tws, tw);
 
   if (MODE == S_INV) {
-    FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tw, BlockSync{});
+    FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tws, BlockSync{});
   } else {
-    FftRun<C, N, E, -1, 1, typename PP::P>::run(v, tt, line, tw, BlockSync{});
+    FftRun<C, N, E, -1, 1, typename PP::P>::run(v, tt, line, tws, BlockSync{});
   }
   if (MODE == S_SYM || MODE == S_SYMA) {
-    const long n2m = (1L << sym.log2_n2) - 1;
-    const double qc = sym.qm[col >> sym.log2_n2] + sym.qx[col & n2m];
+    const int n2 = 1 << sym.log2_n2;
+    const int cl = (int)col;
+    const Rr qc = (Rr)sym.sm * fsq<Rr>(cl >> sym.log2_n2, sym.n1) + (Rr)sym.sx * fsq<Rr>(cl & (n2 - 1), n2);
+    const Rr sa = (Rr)sym.sa;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const Rr p2 = (Rr)(sym.qa[tt + T * e] + qc);
+      const Rr p2 = sa * fsq<Rr>(tt + T * e, N) + qc;
       C m;
       m.x = (Rr)sym.c0r + (Rr)sym.c2r * p2;
       m.y = (Rr)sym.c0i + (Rr)sym.c2i * p2;
       if (MODE == S_SYM) m = crecip(m);
       v[e] = cmul(v[e], cscale(m, (Rr)sym.scale));
     }
-    FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tw, BlockSync{});
+    FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tws, BlockSync{});
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) data[base + (long)(tt + T * e) * S] = v[e];

@@ -222,6 +222,22 @@ class Operator:
                                     _dp(pm), _dp(it)))
         return dict(zip(L.PASS_NAMES, pm.tolist())), float(it[0])
 
+    def get_plan(self) -> dict:
+        p = L.usp_plan()
+        L.check(L.lib().usp_get_plan(self.handle, ct.byref(p)))
+        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream}
+
+    def set_plan(self, x_prefetch=0, w_mid=0, w_sym=0, x_stream=0):
+        p = L.usp_plan(int(x_prefetch), int(w_mid), int(w_sym), int(x_stream))
+        L.check(L.lib().usp_set_plan(self.handle, ct.byref(p)))
+
+    def autotune(self, y, x, alpha=0.8, reps=5) -> dict:
+        """usp_autotune: pick the fastest launch plan (results are identical for all)."""
+        p = L.usp_plan()
+        L.check(L.lib().usp_autotune(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), float(alpha),
+                                     int(reps), ct.byref(p)))
+        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream}
+
     def residual(self, y, x):
         """(||y - A x||/||y||, ||y - A x||, ||y||) in FP64."""
         rel, rn, yn = np.zeros(1), np.zeros(1), np.zeros(1)

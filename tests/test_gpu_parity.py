@@ -206,3 +206,28 @@ def test_nan_is_reported():
     with pytest.raises(_lib.UspError) as ei:
         op.solve(y, alpha=0.8, tol=1e-6, maxit=50, check_every=5)
     assert ei.value.code == _lib.USP_ERR_NAN
+
+
+def test_launch_plans_are_bit_identical_and_autotune_picks_one():
+    """Every autotuner candidate computes the same bits; the tuner keeps a valid plan."""
+    _need_gpu()
+    p = media.helmholtz_spheres(shape=(64, 32, 64), count=5, width=3, w0=3.0, plane=2, seed=12)
+    _announce("plans c64 64x32x64")
+    can, op = gpu_helmholtz(p, "c64")
+    ref = None
+    for pf in (0, 1, 2, 3):
+        for wm in (8, 16, 32):
+            for ws in (8, 16, 32):
+                op.set_plan(pf & 1, wm, ws, pf >> 1)
+                x, h = op.iterate(can.y, alpha=0.8, K=6)
+                xn = x.cpu()
+                if ref is None:
+                    ref = (xn, h)
+                else:
+                    assert torch.equal(xn, ref[0]), (pf, wm, ws)
+                    assert np.array_equal(h, ref[1])
+    xt = torch.zeros_like(can.y)
+    best = op.autotune(can.y, xt, alpha=0.8, reps=3)
+    assert best["w_sym"] in (8, 16, 32) and best["x_prefetch"] in (0, 1)
+    x, _ = op.iterate(can.y, alpha=0.8, K=6)
+    assert torch.equal(x.cpu(), ref[0])
