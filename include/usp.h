@@ -236,6 +236,20 @@ int usp_canonical_helmholtz(const double* k2_host, size_t n, int bias_kind, cons
 int usp_canonical_diffusion(const double* mu_host, size_t n, double D, double omega_over_v, double vnorm,
                             const usp_symbol* grid, usp_symbol* sym_out, double* c_out, double* bias_out);
 
+/* Pantograph canonical form (Sec. 3.3, Eq. pantograph-A) on t_j = t0 + j h:
+ * A x = c^-1 [(d/dt + a) x + b x(lam t)], y = c^-1 [b x0(lam t) + x0(t0) delta(t - t0)],
+ * the delta sampled as x0(t0)/h at j = 0.  Inputs (host, n complex = 2n doubles):
+ * a, b, x0_lam_t (x0(lam t_j) where lam t_j < t0, else 0), x0_t0 (2 doubles).
+ * abar = smallest-circle centre of a; the dilation is a linear-interpolation
+ * gather S; c = (sup|a - abar| + sup|b| ||S||_2)/vnorm (real), which bounds
+ * ||V|| by vnorm.  Outputs (host): sym_out (s = 1/c, a0 = abar, a1 = 1,
+ * nyquist_zero = 1), B_out = 1 - (a - abar)/c, gather idx_out / g0_out / g1_out
+ * (usp_gather layout), y_out, c_out, bias_out (2 doubles each). */
+int usp_canonical_pantograph(const double* a, const double* b, int n, double lam, double t0, double h,
+                             const double* x0_lam_t, const double* x0_t0, double vnorm, usp_symbol* sym_out,
+                             double* B_out, int32_t* idx_out, double* g0_out, double* g1_out, double* y_out,
+                             double* c_out, double* bias_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "
 EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iterate", "usp_residual",
            "usp_destroy", "usp_last_error", "usp_smallest_circle", "usp_canonical_fields",
            "usp_canonical_helmholtz", "usp_canonical_diffusion", "usp_profile", "usp_get_plan", "usp_set_plan",
-           "usp_autotune"]
+           "usp_autotune", "usp_canonical_pantograph"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -82,6 +82,8 @@ def lib():
     L.usp_get_plan.argtypes = [P, PP]
     L.usp_set_plan.argtypes = [P, PP]
     L.usp_autotune.argtypes = [P, P, P, D, I, PP]
+    L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,
+                                           DP, DP, DP]
     for name in EXPORTS:
         if name != "usp_last_error":
             getattr(L, name).restype = ct.c_int

@@ -201,3 +201,106 @@ extern "C" int usp_canonical_diffusion(const double* mu_host, size_t n, double D
   sym_out->a2[0] = D;
   return 0;
 }
+
+// Pantograph (Sec. 3.3, Eq. pantograph-A) on t_j = t0 + j h, j < n:
+//   A x = c^-1 [(d/dt + a) x + b x(lam t)],  y = c^-1 [b x0(lam t) + x0(t0) delta(t - t0)].
+// abar = smallest-circle centre of {a_j}; the dilation x(lam t_j) is a
+// linear-interpolation gather S (entries with lam t_j < t0 belong to the
+// initial condition and are zero in S; the caller's x0(lam t_j) carries them).
+// c = (sup|a - abar| + sup|b| ||S||_2)/vnorm (||S||_2 by power iteration on
+// S^T S), so ||V|| <= vnorm.  Outputs (host arrays of n complex = 2n doubles):
+// B = 1 - (a - abar)/c, the gather weights g0 = b w0 / c, g1 = b w1 / c with
+// indices idx, and y.  Symbol: s = 1/c, a0 = abar, a1 = 1, Nyquist i p = 0.
+extern "C" int usp_canonical_pantograph(const double* a, const double* b, int n, double lam, double t0, double h,
+                                        const double* x0_lam_t, const double* x0_t0, double vnorm,
+                                        usp_symbol* sym_out, double* B_out, int32_t* idx_out, double* g0_out,
+                                        double* g1_out, double* y_out, double* c_out, double* bias_out) {
+  if (!a || !b || !x0_lam_t || !x0_t0 || !sym_out || !B_out || !idx_out || !g0_out || !g1_out || !y_out || !c_out ||
+      !bias_out || n < 2 || !(h > 0.0) || !(lam > 0.0) || !(vnorm > 0.0 && vnorm < 1.0))
+    return USP_ERR_INVALID;
+  double centre[2], Ra;
+  int rc = usp_smallest_circle(a, (size_t)n, USP_BIAS_COMPLEX, centre, &Ra);
+  if (rc) return rc;
+  // interpolation gather
+  std::vector<int> idx(n, 0);
+  std::vector<double> w0(n, 0.0), w1(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const double pos = (lam * (t0 + h * j) - t0) / h;
+    if (pos < -1e-9 || pos > (n - 1) + 1e-9) continue;
+    int i0 = (int)std::floor(pos + 1e-9);
+    double f = pos - i0;
+    if (std::fabs(f) < 1e-9) f = 0.0;
+    if (i0 >= n - 1) {
+      idx[j] = n - 2;
+      w1[j] = 1.0;  // exactly the last sample
+      continue;
+    }
+    idx[j] = i0;
+    w0[j] = 1.0 - f;
+    w1[j] = f;
+  }
+  // ||S||_2 = sqrt(lambda_max(S^T S)).  Each row of S touches two adjacent
+  // columns, so S^T S is symmetric tridiagonal; its largest eigenvalue is found
+  // by bisection on Sturm-sequence counts (to the last bit).
+  std::vector<double> dg(n, 0.0), od(n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    const int i = idx[j];
+    dg[i] += w0[j] * w0[j];
+    dg[i + 1] += w1[j] * w1[j];
+    od[i] += w0[j] * w1[j];
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double q = dg[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = dg[i] - x - od[i - 1] * od[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  double hi = 0.0;
+  for (int i = 0; i < n; ++i) hi = std::max(hi, dg[i] + std::fabs(od[i]) + (i ? std::fabs(od[i - 1]) : 0.0));
+  double lo = 0.0;
+  hi *= 1.0 + 1e-12;
+  for (int it = 0; it < 200 && hi - lo > 1e-16 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n) hi = mid;  // all eigenvalues below mid
+    else lo = mid;
+  }
+  const double snorm = std::sqrt(0.5 * (lo + hi));
+  double bmax = 0.0;
+  for (int j = 0; j < n; ++j) bmax = std::max(bmax, std::hypot(b[2 * j], b[2 * j + 1]));
+  const double c = (Ra + bmax * snorm) / vnorm;
+  if (!(c > 0.0)) return USP_ERR_INVALID;
+  c_out[0] = c;
+  c_out[1] = 0.0;
+  bias_out[0] = centre[0];
+  bias_out[1] = centre[1];
+  *sym_out = usp_symbol{};
+  sym_out->ndim = 1;
+  sym_out->shape[0] = n;
+  sym_out->spacing[0] = h;
+  sym_out->s[0] = 1.0 / c;
+  sym_out->a0[0] = centre[0];
+  sym_out->a0[1] = centre[1];
+  sym_out->a1[0] = 1.0;
+  sym_out->nyquist_zero = 1;
+  for (int j = 0; j < n; ++j) {
+    B_out[2 * j] = 1.0 - (a[2 * j] - centre[0]) / c;
+    B_out[2 * j + 1] = -(a[2 * j + 1] - centre[1]) / c;
+    idx_out[j] = idx[j];
+    g0_out[2 * j] = b[2 * j] * w0[j] / c;
+    g0_out[2 * j + 1] = b[2 * j + 1] * w0[j] / c;
+    g1_out[2 * j] = b[2 * j] * w1[j] / c;
+    g1_out[2 * j + 1] = b[2 * j + 1] * w1[j] / c;
+    // b x0(lam t) / c  (complex product)
+    const double br = b[2 * j], bi = b[2 * j + 1], xr = x0_lam_t[2 * j], xi = x0_lam_t[2 * j + 1];
+    y_out[2 * j] = (br * xr - bi * xi) / c;
+    y_out[2 * j + 1] = (br * xi + bi * xr) / c;
+  }
+  y_out[0] += x0_t0[0] / h / c;
+  y_out[1] += x0_t0[1] / h / c;
+  return 0;
+}

@@ -16,7 +16,7 @@ import torch
 from . import _lib as L
 
 __all__ = ["Operator", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
-           "canonical_diffusion", "canonical_fields"]
+           "canonical_diffusion", "canonical_pantograph", "canonical_fields"]
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -122,6 +122,37 @@ def canonical_diffusion(mu_a, D, omega_over_v, source, spacing, vnorm: float = 0
     S = torch.from_numpy(np.ascontiguousarray(np.asarray(source, dtype=np.complex128))).to(device)
     Bt, yt = canonical_fields(q, S, complex(b[0], b[1]), complex(c[0], c[1]), 1.0, dtype)
     return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
+
+
+@dataclass
+class CanonicalPantograph(Canonical):
+    gather: tuple = None   # (idx int32, g0, g1) device tensors
+
+
+def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm: float = 0.95, dtype=torch.complex128,
+                         device="cuda") -> CanonicalPantograph:
+    """Pantograph canonical form (usp_canonical_pantograph, host) uploaded to the device."""
+    def c128(z):
+        return np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    a, b, x0l = c128(a), c128(b), c128(x0_at_lam_t)
+    n = a.shape[0]
+    x0t = np.array(_c2(x0_t0))
+    sym = L.usp_symbol()
+    Bh = np.zeros(n, np.complex128)
+    idx = np.zeros(n, np.int32)
+    g0 = np.zeros(n, np.complex128)
+    g1 = np.zeros(n, np.complex128)
+    yh = np.zeros(n, np.complex128)
+    c = np.zeros(2)
+    bias = np.zeros(2)
+    f = lambda z: _dp(z.view(np.float64))
+    L.check(L.lib().usp_canonical_pantograph(f(a), f(b), n, float(lam), float(t0), float(h), f(x0l), _dp(x0t),
+                                             float(vnorm), ct.byref(sym), f(Bh),
+                                             idx.ctypes.data_as(ct.POINTER(ct.c_int32)), f(g0), f(g1), f(yh),
+                                             _dp(c), _dp(bias)))
+    T = lambda z: torch.from_numpy(z).to(device=device, dtype=dtype)
+    return CanonicalPantograph(symbol=sym, B=T(Bh), y=T(yh), c=complex(c[0], c[1]), bias=complex(bias[0], bias[1]),
+                               gather=(torch.from_numpy(idx).to(device), T(g0), T(g1)))
 
 
 @dataclass

@@ -85,3 +85,41 @@ def test_host_canonical_helmholtz_matches_oracle():
     assert abs(complex(*b) - cp.bias) < 1e-12 * abs(cp.bias)
     co = solver.symbol_coeffs(out)
     assert abs(co["s"] - cp.s) < 1e-14 and co["a0"] == complex(*b) and co["a2"] == -1
+
+
+def test_host_canonical_pantograph_matches_oracle():
+    """Library pantograph canonical form (power-iteration gather norm) vs the oracle (dense SVD)."""
+    from oracle import canon
+    from paper_2207_14222_amd import _lib, media, solver
+    for bval in (5.0, -5.0):
+        pp = media.pantograph(n=1024, b_value=bval)
+        cp = canon.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0)
+        n = pp.n
+        f = lambda z: np.ascontiguousarray(z, dtype=np.complex128)
+        a, b, x0l = f(pp.a), f(pp.b), f(pp.x0_at_lam_t)
+        dp = lambda z: z.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        sym = _lib.usp_symbol()
+        Bh, g0, g1, yh = (np.zeros(n, np.complex128) for _ in range(4))
+        idx = np.zeros(n, np.int32)
+        c, bias, x0t = np.zeros(2), np.zeros(2), np.array([pp.x0_t0.real, pp.x0_t0.imag])
+        rc = _lib.lib().usp_canonical_pantograph(dp(a), dp(b), n, pp.lam, pp.t0, pp.h, dp(x0l),
+                                                 x0t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 0.95,
+                                                 ctypes.byref(sym), dp(Bh), idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                 dp(g0), dp(g1), dp(yh),
+                                                 c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 bias.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        assert rc == 0
+        assert abs(complex(*c) - cp.c) < 1e-10 * abs(cp.c)
+        assert abs(complex(*bias) - cp.bias) < 1e-12 * abs(cp.bias)
+        assert np.allclose(Bh, cp.B, atol=1e-10) and np.allclose(yh, cp.y, atol=1e-10)
+        # same gather as a matrix (index conventions may differ where weights vanish)
+        So = np.zeros((n, n), complex)
+        Sl = np.zeros((n, n), complex)
+        for j in range(n):
+            So[j, cp.gi[j]] += cp.g0[j]
+            So[j, min(cp.gi[j] + 1, n - 1)] += cp.g1[j]
+            Sl[j, idx[j]] += g0[j]
+            Sl[j, min(idx[j] + 1, n - 1)] += g1[j]
+        assert np.allclose(So, Sl, atol=1e-10)
+        co = solver.symbol_coeffs(sym)
+        assert co["a1"] == 1 and sym.nyquist_zero == 1 and abs(co["s"] - cp.s) < 1e-12

@@ -231,3 +231,25 @@ def test_launch_plans_are_bit_identical_and_autotune_picks_one():
     assert best["w_sym"] in (8, 16, 32) and best["x_prefetch"] in (0, 1)
     x, _ = op.iterate(can.y, alpha=0.8, K=6)
     assert torch.equal(x.cpu(), ref[0])
+
+
+@pytest.mark.parametrize("bval", [5.0, -5.0])
+def test_pantograph_solution_and_iterates(bval):
+    """Pantograph (lambda = 0.5, N = 1024, complex128) with the non-diagonal gather in V."""
+    _need_gpu()
+    from paper_2207_14222_amd import solver
+    pp = media.pantograph(n=1024, b_value=bval)
+    _announce(f"pantograph b={bval}")
+    cp = canon.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0)
+    op_o = operators.Operator(cp)
+    can = solver.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0)
+    op = solver.Operator(can.symbol, can.B, gather=can.gather)
+    xo, ho = R.iterate(op_o, cp.y, 0.9, 15)
+    x, h = op.iterate(can.y, alpha=0.9, K=15)
+    assert rel(to_np(x), xo) < 1e-10
+    ref = R.solve(op_o, cp.y, 0.9, 1e-10, 5000, 1)
+    res = op.solve(can.y, alpha=0.9, tol=1e-10, maxit=5000, check_every=1)
+    assert res.converged and abs(res.iterations - ref.iterations) <= 1
+    assert rel(to_np(res.x), ref.x) < 1e-9
+    xs = np.linalg.solve(op_o.dense_A(), cp.y)
+    assert rel(to_np(res.x), xs) < 1e-8
