@@ -81,6 +81,68 @@ def cpu_baseline(prob, iters_needed, n_iter=3):
             "per_iteration_s": per_it}
 
 
+def bench_batch(args, log):
+    """96 independent 2-D Helmholtz problems (sides drawn from {128, 256, 512, 1024},
+    random disks, beam on row 20; seeds 4 / 4000+i) solved in one persistent launch
+    (complex64 + FP64 refinement every 20, tol 1e-6, alpha 0.8), against solving the
+    same problems one at a time (plain complex128, and refined complex64)."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    sizes = media.batch_sizes(args.batch_n, seed=4)
+    cans, ops = [], []
+    for i, n in enumerate(sizes):
+        p = media.helmholtz_disks(n=n, seed=4000 + i)
+        cans.append(solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex128))
+        ops.append(solver.Operator(cans[-1].symbol, cans[-1].B, refine=True))
+    log(f"batch: {len(sizes)} problems prepared")
+    xs = [torch.zeros_like(c.y) for c in cans]
+    b = solver.Batch(ops, [c.y for c in cans], xs, alpha=args.alpha, tol=args.tol, maxit=20000)
+    variant = b.autotune(refine_every=args.refine_every)
+    b.solve(refine_every=args.refine_every, use_graph=True)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = b.solve(refine_every=args.refine_every, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    log(f"batch: one launch {out.elapsed_ms:.1f} ms device, {wall * 1e3:.1f} ms wall, variant {variant}")
+    # one problem at a time
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op, c in zip(ops, cans):
+        op.solve(c.y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every)
+    torch.cuda.synchronize()
+    seq_ref = time.perf_counter() - t0
+    log(f"batch: sequential refined {seq_ref * 1e3:.1f} ms")
+    ops128 = [solver.Operator(c.symbol, c.B) for c in cans]
+    for op, c in zip(ops128[:2], cans[:2]):
+        op.solve(c.y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its128 = []
+    for op, c in zip(ops128, cans):
+        its128.append(op.solve(c.y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every).iterations)
+    torch.cuda.synchronize()
+    seq_plain = time.perf_counter() - t0
+    log(f"batch: sequential plain complex128 {seq_plain * 1e3:.1f} ms")
+    tdone = np.array(out.t_done_ms)
+    it = np.array(out.iterations)
+    n_pts = int(sum(n * n for n in sizes))
+    per_size = {}
+    for n in sorted(set(sizes)):
+        m = np.array(sizes) == n
+        per_size[str(n)] = {"count": int(m.sum()), "median_ms": round(float(np.median(tdone[m])), 3),
+                            "max_ms": round(float(tdone[m].max()), 3), "median_iterations": int(np.median(it[m]))}
+    return {"n_problems": len(sizes), "points": n_pts, "launches": 1, "graph": True, "variant": variant,
+            "aggregate_time_to_tol_ms": round(out.elapsed_ms, 3), "wall_ms": round(wall * 1e3, 3),
+            "all_converged": bool(all(st == 0 for st in out.status)),
+            "per_problem_time_to_tol_ms": {"median": round(float(np.median(tdone)), 3),
+                                           "p90": round(float(np.percentile(tdone, 90)), 3),
+                                           "max": round(float(tdone.max()), 3)},
+            "per_size": per_size, "max_rho": float(max(out.rho)),
+            "sequential_refined_ms": round(seq_ref * 1e3, 3), "sequential_plain_c128_ms": round(seq_plain * 1e3, 3),
+            "speedup_vs_sequential_plain": round(seq_plain * 1e3 / out.elapsed_ms, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +156,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the plain complex128/complex64 reference solves")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
+    ap.add_argument("--batch-n", type=int, default=96)
     ap.add_argument("--plan", default=None, help="force a launch plan 'x_prefetch,w_mid,w_sym,x_stream' (no tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -216,6 +280,11 @@ def main():
                               "min_rho": float(np.min(r64.hist_true[:, 1])),
                               "reaches_tol": bool(r64.converged)}
         del op64, r64, can64
+        torch.cuda.empty_cache()
+
+    if not args.no_batch:
+        log("batched 2-D workload")
+        extra["batched"] = bench_batch(args, log)
         torch.cuda.empty_cache()
 
     cpu = None

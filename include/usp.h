@@ -196,6 +196,56 @@ int usp_set_plan(usp_op op, const usp_plan* plan);
  * all candidates are identical, so tuning never changes a solution. */
 int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int reps, usp_plan* best_out);
 
+/* ---- batched persistent solve (many uneven-size 2-D problems) ----------- */
+
+/* One problem of a batch: a square 2-D operator prepared with
+ * USP_FLAG_REFINE (its workspace holds the problem's scratch), the
+ * complex128 right-hand side and solution buffers, and the solve settings. */
+typedef struct {
+  usp_op op;
+  const void* y_dev;
+  void* x_dev;
+  int x_is_guess;
+  double alpha;
+  double tol;
+  int maxit;
+} usp_batch_item;
+
+typedef struct {
+  int iterations;    /* complex64 iterations performed */
+  int status;        /* 0 converged, 1 maxit, 2 stagnated, < 0 error */
+  double rho;        /* last ||y - A x||/||y|| (FP64) */
+  double t_done_ms;  /* device time from the first workgroup's start to this problem's end */
+} usp_batch_result;
+
+/* Device workspace (problem table, task lists, states, partial sums) for a batch. */
+int usp_batch_workspace_bytes(const usp_batch_item* items, int nprob, size_t* bytes);
+
+/* Solve every item with the refined method (complex64 iterations of
+ * Algorithm 1, FP64 residual recomputed and accumulated every refine_every
+ * iterations, stop at ||y - A x||/||y|| < tol; maxit is rounded up to a
+ * multiple of refine_every).  variant: bits 0-1 select the fused-pass access
+ * plan (bit 0 prefetch, bit 1 streaming); bit 2 selects the schedule:
+ *   0 grouped: every launch covers the tiles of all active problems (the whole
+ *     chip works on the batch); per-problem convergence, status and
+ *     timestamps are decided on the device; with use_graph = 1 one refinement
+ *     cycle is captured in a hipGraph and replayed (re-captured when the
+ *     active work shrinks by a quarter);
+ *   4 persistent: ONE launch (captured in a hipGraph when use_graph = 1) in
+ *     which each workgroup takes whole problems, largest first, from a ticket
+ *     counter and solves them alone; workgroups never wait for each other.
+ * Graphs run on a private default-priority stream ordered after `stream`.
+ * results (host, may be NULL; in item order) and elapsed_ms (device time) are
+ * filled in.  Returns the worst status (errors < 0 first). */
+int usp_solve_batched(const usp_batch_item* items, int nprob, int refine_every, int variant, void* workspace_dev,
+                      size_t workspace_bytes, void* stream, int use_graph, usp_batch_result* results,
+                      double* elapsed_ms);
+
+/* Autotuner of the batched solve: runs 2 * refine_every iterations of every
+ * problem with each variant (0..7) and returns the fastest (overwrites x_dev). */
+int usp_autotune_batched(const usp_batch_item* items, int nprob, int refine_every, void* workspace_dev,
+                         size_t workspace_bytes, void* stream, int* best_variant);
+
 /* Destroy a handle (frees host memory only). */
 int usp_destroy(usp_op op);
 

@@ -25,7 +25,8 @@ STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "
 EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iterate", "usp_residual",
            "usp_destroy", "usp_last_error", "usp_smallest_circle", "usp_canonical_fields",
            "usp_canonical_helmholtz", "usp_canonical_diffusion", "usp_profile", "usp_get_plan", "usp_set_plan",
-           "usp_autotune", "usp_canonical_pantograph"]
+           "usp_autotune", "usp_canonical_pantograph", "usp_batch_workspace_bytes", "usp_solve_batched",
+           "usp_autotune_batched"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -38,6 +39,15 @@ class usp_symbol(ct.Structure):
 
 class usp_plan(ct.Structure):
     _fields_ = [("x_prefetch", ct.c_int), ("w_mid", ct.c_int), ("w_sym", ct.c_int), ("x_stream", ct.c_int)]
+
+
+class usp_batch_item(ct.Structure):
+    _fields_ = [("op", ct.c_void_p), ("y_dev", ct.c_void_p), ("x_dev", ct.c_void_p), ("x_is_guess", ct.c_int),
+                ("alpha", ct.c_double), ("tol", ct.c_double), ("maxit", ct.c_int)]
+
+
+class usp_batch_result(ct.Structure):
+    _fields_ = [("iterations", ct.c_int), ("status", ct.c_int), ("rho", ct.c_double), ("t_done_ms", ct.c_double)]
 
 
 class usp_gather(ct.Structure):
@@ -82,6 +92,10 @@ def lib():
     L.usp_get_plan.argtypes = [P, PP]
     L.usp_set_plan.argtypes = [P, PP]
     L.usp_autotune.argtypes = [P, P, P, D, I, PP]
+    BI = ct.POINTER(usp_batch_item)
+    L.usp_batch_workspace_bytes.argtypes = [BI, I, ct.POINTER(Z)]
+    L.usp_solve_batched.argtypes = [BI, I, I, I, P, Z, P, I, ct.POINTER(usp_batch_result), DP]
+    L.usp_autotune_batched.argtypes = [BI, I, I, P, Z, P, IP]
     L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,
                                            DP, DP, DP]
     for name in EXPORTS:

@@ -45,8 +45,6 @@ template <class R> __device__ __forceinline__ R fsq(int k, int n) {
   return (R)(f * f);
 }
 
-// Contiguous-axis pass.  Cc: compute (and spectrum storage) type; Cx: storage
-// type of x, y, B.
 // streaming (non-temporal) global access for fields read or written once per
 // pass, so that they do not evict the temporary spectrum from the caches
 template <class C> __device__ __forceinline__ C ld_stream(const C* p) {
@@ -84,30 +82,50 @@ template <bool NT, class C> __device__ __forceinline__ void st(C* p, C v) {
   else *p = v;
 }
 
+// Number of block barriers one FFT of plan P executes (two per LDS exchange);
+// threads that sit out an FFT execute the same number so barriers match.
+template <int N, class P> struct FftSyncs;
+template <int N> struct FftSyncs<N, Plan<>> { static constexpr int value = 0; };
+template <int N, int R0, int... Rest> struct FftSyncs<N, Plan<R0, Rest...>> {
+  static constexpr int value = (sizeof...(Rest) > 0 ? 2 : 0) + FftSyncs<N, Plan<Rest...>>::value;
+};
+template <int N, class P> __device__ __forceinline__ void idle_fft_syncs() {
+#pragma unroll
+  for (int i = 0; i < FftSyncs<N, P>::value; ++i) __syncthreads();
+}
+
+// Contiguous-axis pass.  Cc: compute (and spectrum storage) type; Cx: storage
+// type of x, y, B.  Body for LPB lines starting at line0 (TH = LPB*T
+// threads take part; threads >= TH only join the barriers and must form whole
+// waves).  tws: twiddles in LDS; lds: LPB padded rows.  Returns the thread's
+// partial sum of |Delta|^2 (X_FUSED) or |r|^2 (X_RINV).
 // FL (fused pass only): bit 0 = load x, B, y before the inverse FFT;
-// bit 1 = stream x, B, y (non-temporal loads / store)
-template <class Cc, class Cx, int N, int MODE, int FL = 0>
-__global__ void __launch_bounds__(x_threads<Cc>())
-k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const Cx* __restrict__ B,
-        const float2* __restrict__ d, float2* __restrict__ r32, const Cc* __restrict__ tw, double alpha,
-        int nlines, int has_x, RedArgs red) {
+// bit 1 = stream x, B, y (non-temporal loads / store).
+template <class Cc, class Cx, int N, int MODE, int FL, int LPB>
+__device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y,
+                                             const Cx* __restrict__ B, const float2* __restrict__ d,
+                                             float2* __restrict__ r32, const Cc* tws, Cc* lds, double alpha,
+                                             long line0, long nlines, int has_x) {
   using Rr = typename real_of<Cc>::type;
   using PP = PassPlan<N>;
   constexpr int E = PP::E, T = N / E;
-  constexpr int TPB = x_threads<Cc>();
-  constexpr int LPB = (TPB / T) > 0 ? (TPB / T) : 1;
+  constexpr int TH = LPB * T;
   constexpr int PADN = LdsRow<Cc>::padded(N);
-  __shared__ Cc lds[LPB * PADN];
-  __shared__ Cc tws[N];
-  __shared__ double scratch[64];
-
   const int tid = threadIdx.x;
-  load_twiddles<Cc, N>(tws, tw);
+  if (tid >= TH) {
+    if (MODE == X_FUSED) {
+      idle_fft_syncs<N, typename PP::P>();
+      idle_fft_syncs<N, typename PP::P>();
+    } else {
+      idle_fft_syncs<N, typename PP::P>();
+    }
+    return 0.0;
+  }
   const int tt = tid % T, li = tid / T;
-  const long line = (long)blockIdx.x * LPB + li;
-  const bool active = (li < LPB) && (line < nlines);
+  const long line = line0 + li;
+  const bool active = line < nlines;
   const long base = line * N;
-  LdsRow<Cc> row{lds + (li < LPB ? li : 0) * PADN};
+  LdsRow<Cc> row{lds + li * PADN};
   Cc v[E];
   double acc = 0.0;
 
@@ -118,7 +136,8 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
       Cc val = mk<Cc>(0.0, 0.0);
       if (active) {
         val = cvt<Cc>(y[p]);
-        if (has_x) val = cadd(val, cmul(cvt<Cc>(B[p]), cvt<Cc>(x[p])));
+        if (has_x == 1) val = cadd(val, cmul(cvt<Cc>(B[p]), cvt<Cc>(x[p])));
+        if (has_x == 2) x[p] = cvt<Cx>(mk<Cc>(0.0, 0.0));  // start of an inner solve: x = 0
       }
       v[e] = val;
     }
@@ -127,7 +146,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
-    return;
+    return 0.0;
   }
 
   if (MODE == X_FUSED) {
@@ -169,14 +188,7 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
-    block_partial(acc, scratch, red.row);
-    return;
-  }
-
-  if (MODE == X_RINV) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = active ? t[base + tt + T * e] : mk<Cc>(0.0, 0.0);
-    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    return acc;
   }
 
   if (MODE == X_RFWD) {
@@ -198,26 +210,43 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
-    return;
+    return 0.0;
   }
 
-  if (MODE == X_RINV) {
+  // X_RINV
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (active) {
-        const long p = base + tt + T * e;
-        const Cc xx = cvt<Cc>(x[p]);
-        const Cc bb = cvt<Cc>(B[p]);
-        const Cc yy = cvt<Cc>(y[p]);
-        // r = y - L x - (1 - B) x
-        const Cc r = cadd(csub(csub(yy, v[e]), xx), cmul(bb, xx));
-        acc += cabs2(r);
-        if (r32) r32[p] = cvt<float2>(r);
-      }
+  for (int e = 0; e < E; ++e) v[e] = active ? t[base + tt + T * e] : mk<Cc>(0.0, 0.0);
+  FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (active) {
+      const long p = base + tt + T * e;
+      const Cc xx = cvt<Cc>(x[p]);
+      const Cc bb = cvt<Cc>(B[p]);
+      const Cc yy = cvt<Cc>(y[p]);
+      // r = y - L x - (1 - B) x
+      const Cc r = cadd(csub(csub(yy, v[e]), xx), cmul(bb, xx));
+      acc += cabs2(r);
+      if (r32) r32[p] = cvt<float2>(r);
     }
-    block_partial(acc, scratch, red.row);
-    return;
   }
+  return acc;
+}
+
+template <class Cc, class Cx, int N, int MODE, int FL = 0>
+__global__ void __launch_bounds__(x_threads<Cc>())
+k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const Cx* __restrict__ B,
+        const float2* __restrict__ d, float2* __restrict__ r32, const Cc* __restrict__ tw, double alpha,
+        int nlines, int has_x, RedArgs red) {
+  constexpr int T = N / PassPlan<N>::E;
+  constexpr int LPB = (x_threads<Cc>() / T) > 0 ? (x_threads<Cc>() / T) : 1;
+  __shared__ Cc lds[LPB * LdsRow<Cc>::padded(N)];
+  __shared__ Cc tws[N];
+  __shared__ double scratch[64];
+  load_twiddles<Cc, N>(tws, tw);
+  const double acc = xpass_body<Cc, Cx, N, MODE, FL, LPB>(t, x, y, B, d, r32, tws, lds, alpha,
+                                                         (long)blockIdx.x * LPB, nlines, has_x);
+  if (MODE == X_FUSED || MODE == X_RINV) block_partial(acc, scratch, red.row);
 }
 
 // Strided-axis pass over a tile of W adjacent columns.  Element (pos, col, b)
@@ -235,23 +264,31 @@ template <class C> constexpr bool s_width_ok(int N, int W, int E) {
   return (N * (W + 1) + N) * (int)sizeof(C) <= 160 * 1024 && W * (N / E) <= 1024;
 }
 
+// Body of the strided pass for columns col0 .. col0 + W - 1 of batch b.
+// Threads >= W*T only join the barriers (whole waves, or no barriers at all
+// for single-stage plans).  If tw_g is non-NULL the twiddles are copied into
+// tws after the column loads are issued.
 template <class C, int N, int W, int MODE>
-__global__ void __launch_bounds__(W * (N / PassPlan<N>::E))
-k_spass(C* __restrict__ data, const C* __restrict__ tw, long S, SymArgs sym) {
+__device__ __forceinline__ void spass_body(C* __restrict__ data, const C* __restrict__ tw_g, C* tws, C* lds, long S,
+                                           const SymArgs& sym, long col0, long b) {
   using Rr = typename real_of<C>::type;
   using PP = PassPlan<N>;
   constexpr int E = PP::E, T = N / E;
-  __shared__ C lds[N * (W + 1)];
-  __shared__ C tws[N];
   const int tid = threadIdx.x;
+  if (tid >= W * T) {
+    if (tw_g) load_twiddles<C, N>(tws, tw_g);
+    idle_fft_syncs<N, typename PP::P>();
+    if (MODE == S_SYM || MODE == S_SYMA) idle_fft_syncs<N, typename PP::P>();
+    return;
+  }
   const int c = tid % W, tt = tid / W;
-  const long col = (long)blockIdx.x * W + c;
-  const long base = (long)blockIdx.y * N * S + col;
+  const long col = col0 + c;
+  const long base = b * N * S + col;
   LdsCol<C, W> line{lds + c};
   C v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = data[base + (long)(tt + T * e) * S];
-  load_twiddles<C, N>(tws, tw);
+  if (tw_g) load_twiddles<C, N>(tws, tw_g);
 
   if (MODE == S_INV) {
     FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tws, BlockSync{});
@@ -276,6 +313,14 @@ k_spass(C* __restrict__ data, const C* __restrict__ tw, long S, SymArgs sym) {
   }
 #pragma unroll
   for (int e = 0; e < E; ++e) data[base + (long)(tt + T * e) * S] = v[e];
+}
+
+template <class C, int N, int W, int MODE>
+__global__ void __launch_bounds__(W * (N / PassPlan<N>::E))
+k_spass(C* __restrict__ data, const C* __restrict__ tw, long S, SymArgs sym) {
+  __shared__ C lds[N * (W + 1)];
+  __shared__ C tws[N];
+  spass_body<C, N, W, MODE>(data, tw, tws, lds, S, sym, (long)blockIdx.x * W, (long)blockIdx.y);
 }
 
 }  // namespace usp

@@ -275,3 +275,53 @@ class Operator:
         L.check(L.lib().usp_residual(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), _dp(rel), _dp(rn),
                                      _dp(yn)))
         return float(rel[0]), float(rn[0]), float(yn[0])
+
+
+@dataclass
+class BatchResult:
+    iterations: list
+    status: list
+    rho: list
+    t_done_ms: list
+    elapsed_ms: float
+    worst: int
+
+
+class Batch:
+    """Many independent square 2-D refined problems solved together (usp_solve_batched).
+    ops: refined Operators; ys / xs: complex128 tensors.  variant: bits 0-1 fused-pass
+    plan, bit 2 persistent one-launch schedule (else grouped launches)."""
+
+    def __init__(self, ops, ys, xs, alpha=0.8, tol=1e-6, maxit=20000):
+        if not (len(ops) == len(ys) == len(xs)) or not ops:
+            raise ValueError("ops, ys, xs must have the same non-zero length")
+        self.ops, self.ys, self.xs = ops, ys, xs
+        self.n = len(ops)
+        arr = (L.usp_batch_item * self.n)()
+        for i, (op, y, x) in enumerate(zip(ops, ys, xs)):
+            arr[i] = L.usp_batch_item(op.handle.value, y.data_ptr(), x.data_ptr(), 0, float(alpha), float(tol),
+                                      int(maxit))
+        self.items = arr
+        nb = ct.c_size_t()
+        L.check(L.lib().usp_batch_workspace_bytes(self.items, self.n, ct.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ops[0].device)
+        self.ws_bytes = nb.value
+        self.variant = 0
+
+    def autotune(self, refine_every=20) -> int:
+        v = ct.c_int()
+        L.check(L.lib().usp_autotune_batched(self.items, self.n, int(refine_every), _ptr(self.ws), self.ws_bytes,
+                                             _stream_ptr(self.ws.device), ct.byref(v)))
+        self.variant = v.value
+        return v.value
+
+    def solve(self, refine_every=20, use_graph=True, variant=None) -> BatchResult:
+        res = (L.usp_batch_result * self.n)()
+        ms = np.zeros(1)
+        v = self.variant if variant is None else int(variant)
+        rc = L.check(L.lib().usp_solve_batched(self.items, self.n, int(refine_every), v, _ptr(self.ws),
+                                               self.ws_bytes, _stream_ptr(self.ws.device), int(bool(use_graph)),
+                                               res, _dp(ms)))
+        return BatchResult(iterations=[r.iterations for r in res], status=[r.status for r in res],
+                           rho=[r.rho for r in res], t_done_ms=[r.t_done_ms for r in res],
+                           elapsed_ms=float(ms[0]), worst=rc)
