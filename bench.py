@@ -81,6 +81,30 @@ def cpu_baseline(prob, iters_needed, n_iter=3):
             "per_iteration_s": per_it}
 
 
+def bench_diffusion(args, log):
+    """Frequency-domain diffusion, 256 x 256 x 128 (constant D = 0.03 cm, log-normal mu_a
+    blobs, 100 MHz, seed 3), alpha = 1: plain complex64, plain complex128 and complex64 +
+    FP64 refinement every 20 iterations, each to ||r||/||y|| < 1e-6."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    d = media.diffusion_blobs(seed=3)
+    out = {"grid": list(d.shape), "alpha": 1.0, "tol": args.tol}
+    for name, dt, refine in (("plain_c64", torch.complex64, False), ("plain_c128", torch.complex128, False),
+                             ("refined_c64", torch.complex128, True)):
+        can = solver.canonical_diffusion(d.mu_a, d.D, d.omega_over_v, d.source, d.spacing, dtype=dt)
+        op = solver.Operator(can.symbol, can.B, refine=refine)
+        op.solve(can.y, alpha=1.0, tol=args.tol, maxit=5000, check_every=args.refine_every)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.solve(can.y, alpha=1.0, tol=args.tol, maxit=5000, check_every=args.refine_every)
+        torch.cuda.synchronize()
+        out[name] = {"time_ms": round((time.perf_counter() - t0) * 1e3, 3), "iterations": r.iterations,
+                     "status": r.status_name, "rho": float(r.hist_true[-1, 1])}
+        log(f"diffusion {name}: {out[name]}")
+        del op, can
+    return out
+
+
 def bench_batch(args, log):
     """96 independent 2-D Helmholtz problems (sides drawn from {128, 256, 512, 1024},
     random disks, beam on row 20; seeds 4 / 4000+i) solved in one persistent launch
@@ -132,7 +156,8 @@ def bench_batch(args, log):
         m = np.array(sizes) == n
         per_size[str(n)] = {"count": int(m.sum()), "median_ms": round(float(np.median(tdone[m])), 3),
                             "max_ms": round(float(tdone[m].max()), 3), "median_iterations": int(np.median(it[m]))}
-    return {"n_problems": len(sizes), "points": n_pts, "launches": 1, "graph": True, "variant": variant,
+    return {"n_problems": len(sizes), "points": n_pts, "graph": True, "variant": variant,
+            "schedule": "persistent one-launch" if variant & 4 else "grouped launches, one captured graph per refinement cycle",
             "aggregate_time_to_tol_ms": round(out.elapsed_ms, 3), "wall_ms": round(wall * 1e3, 3),
             "all_converged": bool(all(st == 0 for st in out.status)),
             "per_problem_time_to_tol_ms": {"median": round(float(np.median(tdone)), 3),
@@ -280,6 +305,11 @@ def main():
                               "min_rho": float(np.min(r64.hist_true[:, 1])),
                               "reaches_tol": bool(r64.converged)}
         del op64, r64, can64
+        torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        log("diffusion workload")
+        extra["diffusion"] = bench_diffusion(args, log)
         torch.cuda.empty_cache()
 
     if not args.no_batch:
