@@ -14,7 +14,11 @@ default solver: complex64 iterations with the residual recomputed and
 accumulated in FP64 every 20 iterations.  Inputs (B, y) are resident in HBM
 before the timed region.  Reported beside it: the plain complex128 solve, the
 plain complex64 solve's attainable residual, per-pass kernel times (hipEvents
-on the solver's stream), and the FP64 CPU oracle timed on a bounded sample.
+on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
+the other workloads under "modes": diffusion (plain vs refined), 96 batched
+2-D problems in one graph-captured schedule, and the learned initial guess
+on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
+protocol is 2000 / 200 media).
 """
 from __future__ import annotations
 
@@ -27,6 +31,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0   # dense bf16 matrix-core peak (MI355X)
 METRIC = "time to ‖r‖/‖y‖<1e-6 + GB/s/iter, 256³ Helmholtz; plain vs learned-x0 vs batched"
 
 
@@ -168,6 +173,40 @@ def bench_batch(args, log):
             "speedup_vs_sequential_plain": round(seq_plain * 1e3 / out.elapsed_ms, 2)}
 
 
+def bench_learned(args, log):
+    """Learned initial guess on 128^3 random-sphere media (shared canonical scaling):
+    training data from solves of the method (seeds 0..), Adam training of the
+    3-D network, then on held-out media (seeds 10000..) the solve from x0 = 0
+    against network inference + residual check + solve from the learned x0,
+    and the plain complex128 solve."""
+    import torch
+    from paper_2207_14222_amd import learned, surrogate
+    res, net, _ = learned.run((128, 128, 128), n_train=args.learned_train, n_test=args.learned_test,
+                              epochs=args.learned_epochs, lr=2e-3, log=log)
+    # network forward alone: executed matrix-core flops (padded channels) per launch sequence
+    flops = 0
+    for name, cin, cout, taps in surrogate.LAYERS:
+        d, h, w = net.levels[net._level(name)]
+        flops += 2 * d * h * w * taps * cin * cout
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.forward()
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / 10
+    res["forward_ms"] = round(fwd_ms, 3)
+    res["forward_TFLOP/s"] = round(flops / (fwd_ms * 1e-3) / 1e12, 1)
+    res["forward_frac_bf16_peak"] = round(flops / (fwd_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)
+    res["forward_flops"] = flops
+    for k, v in list(res.items()):
+        if isinstance(v, float):
+            res[k] = float(f"{v:.5g}")
+    log(f"learned x0: {res}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -183,6 +222,10 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
     ap.add_argument("--batch-n", type=int, default=96)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess workload")
+    ap.add_argument("--learned-train", type=int, default=600, help="training media (the full protocol uses 2000)")
+    ap.add_argument("--learned-test", type=int, default=30, help="held-out media (the full protocol uses 200)")
+    ap.add_argument("--learned-epochs", type=int, default=4)
     ap.add_argument("--plan", default=None, help="force a launch plan 'x_prefetch,w_mid,w_sym,x_stream' (no tuning)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -315,6 +358,11 @@ def main():
     if not args.no_batch:
         log("batched 2-D workload")
         extra["batched"] = bench_batch(args, log)
+        torch.cuda.empty_cache()
+
+    if not args.no_learned:
+        log("learned initial guess workload (128^3)")
+        extra["learned_x0"] = bench_learned(args, log)
         torch.cuda.empty_cache()
 
     cpu = None

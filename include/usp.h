@@ -305,26 +305,40 @@ int usp_canonical_pantograph(const double* a, const double* b, int n, double lam
  * A learned x0 (a network mapping the refractive-index map to the field) is
  * an extension of the method: the fixed-point iteration (Algorithm 1)
  * starts from it and is the judge of its error, falling back to x0 = 0 when
- * ||y - A x0|| >= ||y||.  Tensors are channels-last: activations [V][C]
- * bf16 (16-bit words, round-to-nearest-even), V = D*H*W voxels with x
- * fastest, C a multiple of 16 (inputs padded); conv weights [COUT][TAPS][CIN]
- * bf16 with an fp32 master copy; biases fp32.  All calls run on `stream`
+ * ||y - A x0|| >= ||y||.  Activations are bf16 (16-bit words,
+ * round-to-nearest-even) in 16-channel planes: a tensor with C channels (C
+ * a multiple of 16; inputs padded) over V = D*H*W voxels (x fastest) holds
+ * element (v, c) at ((c / 16) * V + v) * 16 + c % 16, so concatenation along
+ * channels is placing planes one after the other.  Conv weights
+ * [COUT][TAPS][CIN] bf16 with an fp32 master copy, repacked for the kernels
+ * by usp_nn_pack_weights; biases fp32.  All calls run on `stream`
  * (asynchronous unless stated) and allocate nothing.
  */
 
+/* Repack bf16 weights w [cout][taps][cin] (the forward layer's) into the
+ * fragment order usp_nn_conv3d reads: transposed 0 for the forward
+ * convolution (cin -> cout), 1 for the input gradient (cout -> cin).  The
+ * packed array has taps * cin * cout bf16.  cin, cout multiples of 16, taps
+ * 1 or 27, else USP_ERR_INVALID. */
+int usp_nn_pack_weights(const void* w_dev, void* packed_dev, int cout, int taps, int cin, int transposed, void* stream);
+
 /* 3x3x3 (taps 27, zero padding 1) or 1x1x1 (taps 1) convolution as an
- * implicit GEMM on the bf16 matrix cores with fp32 accumulation:
+ * implicit GEMM on the bf16 matrix cores with fp32 accumulation, from cin to
+ * cout channels with weights packed by usp_nn_pack_weights:
  *   sign +1: out[v][co] = act(bias[co] + sum_{tap,ci} in[v + off(tap)][ci] w[co][tap][ci])
- *   sign -1: input gradient, with w in the transposed layout
- *            [CIN_fwd][TAPS][COUT_fwd] (usp_nn_transpose_weights) and no bias/ReLU.
- * relu: apply max(0, .); bias may be NULL.  The first cstore output channels
- * are written with row pitch cstore, as bf16 or (out_f32) fp32.  V must be a
- * multiple of 16.  Supported (cin, cout, taps): the network's layer shapes
- * (16,16), (16,32), (32,16), (32,32), (32,64), (64,32), (64,64), (64,128),
- * (128,64), (192,64), (64,192), (96,32), (32,96), (48,16), (16,48) with 27
- * taps and (16,16) with 1 tap; others: USP_ERR_UNSUPPORTED_SHAPE. */
-int usp_nn_conv3d(const void* in_dev, const void* w_dev, const float* bias_dev, void* out_dev, int out_f32, int cstore,
-                  int D, int H, int W, int cin, int cout, int taps, int sign, int relu, void* stream);
+ *            (packing with transposed 0 of the layer's weights);
+ *   sign -1: input gradient of a layer whose forward direction is cout -> cin,
+ *            out[v][ci] = sum_{tap,co} g[v - off(tap)][co] w[co][tap][ci]
+ *            (packing with transposed 1; no bias, no ReLU).
+ * relu: apply max(0, .); bias may be NULL.  bf16 output: all cout channels
+ * as planes (cstore must equal cout); out_f32: fp32 rows [V][cstore] of the
+ * first cstore channels.  V must be a multiple of 16 and at most 2^30.
+ * Supported (cin, cout, taps): the network's layer shapes (16,16), (16,32),
+ * (32,16), (32,32), (32,64), (64,32), (64,64), (64,128), (128,64), (192,64),
+ * (64,192), (96,32), (32,96), (48,16), (16,48) with 27 taps and (16,16)
+ * with 1 tap; others: USP_ERR_UNSUPPORTED_SHAPE. */
+int usp_nn_conv3d(const void* in_dev, const void* wpacked_dev, const float* bias_dev, void* out_dev, int out_f32,
+                  int cstore, int D, int H, int W, int cin, int cout, int taps, int sign, int relu, void* stream);
 
 /* Weight (and bias) gradient of usp_nn_conv3d (sign +1):
  *   dw[co][tap][ci] = sum_v in[v + off(tap)][ci] g[v][co],  db[co] = sum_v g[v][co]
@@ -334,17 +348,19 @@ int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, siz
 int usp_nn_conv3d_wgrad(const void* in_dev, const void* g_dev, float* dw_dev, float* db_dev, void* ws_dev,
                         size_t ws_bytes, int D, int H, int W, int cin, int cout, int taps, void* stream);
 
-/* 2x2x2 average pooling of a D x H x W grid (backward 0: in fine, out coarse;
- * backward 1: in = coarse gradient, out = fine gradient). */
+/* 2x2x2 average pooling of a D x H x W grid (even sides; backward 0: in
+ * fine, out coarse; backward 1: in = coarse gradient, out = fine gradient). */
 int usp_nn_pool2(const void* in_dev, void* out_dev, int D, int H, int W, int C, int backward, void* stream);
 
 /* Nearest upsampling by 2 to a D x H x W grid, written to channels
  * [c0, c0 + C) of an output with Ctot channels (backward 1: in = fine
- * gradient with Ctot channels, out = coarse gradient of those C channels). */
+ * gradient with Ctot channels, out = coarse gradient of those C channels).
+ * c0 and C multiples of 16. */
 int usp_nn_upsample2(const void* in_dev, void* out_dev, int D, int H, int W, int C, int Ctot, int c0, int backward,
                      void* stream);
 
-/* dst[v][d0 + c] = src[v][s0 + c] for c < C (concatenation / split). */
+/* dst[v][d0 + c] = src[v][s0 + c] for c < C (concatenation / split; whole
+ * planes: s0, d0, C multiples of 16). */
 int usp_nn_channel_copy(const void* src_dev, int Cs, int s0, void* dst_dev, int Cd, int d0, int C, long V, void* stream);
 
 /* out = g * (y > 0) (y: post-ReLU activation); accumulate 1: out += that. */
@@ -353,11 +369,16 @@ int usp_nn_relu_backward(const void* y_dev, const void* g_dev, void* out_dev, lo
 /* dst += src (bf16, n elements). */
 int usp_nn_add(void* dst_dev, const void* src_dev, long n, void* stream);
 
-/* Network input from the complex refractive index (complex64 [V]): channel 0
- * (Re n - n_bg)/n_span, channel 1 kappa/kappa_max, channel 2 = 1 on the
- * source plane z == plane, channels 3..15 zero (bf16 [V][16]). */
+/* Network input from the complex refractive index n + i kappa (complex64
+ * [D][H][W]), one plane of 16 bf16 channels: 0 (Re n - n_bg)/n_span,
+ * 1 kappa/kappa_max, 2 = 1 on the source plane z == plane, 3 and 4 the real
+ * and imaginary parts of the source's Gaussian beam
+ * exp(-((x - W/2)^2 + (y - H/2)^2)/w0^2) carried along z with
+ * exp(i k0h S(z)), S(z) the trapezoidal sum of n + i kappa between the
+ * source plane and z (k0h = wavenumber times grid step), 5..15 zero.
+ * 0 <= plane < D, n_span, kappa_max, w0 > 0, else USP_ERR_INVALID. */
 int usp_nn_features(const void* nidx_dev, void* out_dev, int D, int H, int W, double n_bg, double n_span,
-                    double kappa_max, int plane, void* stream);
+                    double kappa_max, int plane, double k0h, double w0, void* stream);
 
 /* Relative squared L2 loss ||scale p - x||^2 / ||x||^2 between the prediction
  * p (fp32 [V][2], Re/Im) and the target field x (complex64 [V]); grad (may be
@@ -370,9 +391,6 @@ int usp_nn_loss(const float* pred_dev, const void* target_dev, float scale, long
  * wb (may be NULL) receives the bf16 copy. */
 int usp_nn_adam(float* w_dev, const float* g_dev, float* m_dev, float* v_dev, void* wb_dev, long n, float lr, float b1,
                 float b2, float eps, int step, void* stream);
-
-/* [COUT][TAPS][CIN] -> [CIN][TAPS][COUT] (bf16), for the input gradient. */
-int usp_nn_transpose_weights(const void* w_dev, void* wt_dev, int cout, int taps, int cin, void* stream);
 
 /* fp32 -> bf16 (n elements). */
 int usp_nn_to_bf16(const float* a_dev, void* b_dev, long n, void* stream);

@@ -9,16 +9,47 @@ concatenates the encoder output of that level (skip first) and applies one
 3x3x3 convolution + ReLU (192->64, 96->32, 48->16); a 1x1x1 convolution
 gives (Re, Im).  Tensors here are channels-first [C, D, H, W] in float64.
 The loss is the relative squared L2 error ||s p - x||^2 / ||x||^2.
+
+The 5 input channels (``features``) are functions of the complex index map
+n + i kappa and of the fixed source geometry: the scaled index, the scaled
+absorption, the source-plane indicator, and the Gaussian beam of the source
+carried along the axis of propagation with the phase and attenuation of the
+medium it crosses (the optical path k0 h sum (n + i kappa), trapezoidal
+between grid planes, from the source plane in both directions).
 """
 from __future__ import annotations
+
+
+import numpy as np
 
 import torch
 import torch.nn.functional as F
 
-ENC = [("e1a", 3, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32), ("e3a", 32, 64), ("e3b", 64, 64)]
+ENC = [("e1a", 5, 16), ("e1b", 16, 16), ("e2a", 16, 32), ("e2b", 32, 32), ("e3a", 32, 64), ("e3b", 64, 64)]
 BOTTLENECK = ("b", 64, 128)
 DEC = [("d3", 64 + 128, 64), ("d2", 32 + 64, 32), ("d1", 16 + 32, 16)]
 HEAD = ("head", 16, 2)
+
+
+def features(nidx, plane, w0, k0h, n_bg=1.33, n_span=0.17, kappa_max=0.2):
+    """Input channels [5, D, H, W] (float64 numpy) from the complex index nidx [D, H, W]."""
+    D, H, W = nidx.shape
+    f = np.zeros((5, D, H, W))
+    f[0] = (nidx.real - n_bg) / n_span
+    f[1] = nidx.imag / kappa_max
+    f[2, plane] = 1.0
+    yy = np.arange(H)[:, None] - H / 2
+    xx = np.arange(W)[None, :] - W / 2
+    amp = np.exp(-(xx ** 2 + yy ** 2) / w0 ** 2)
+    for z in range(D):
+        lo, hi = min(z, plane), max(z, plane)
+        path = np.zeros((H, W), dtype=complex)
+        for q in range(lo, hi):          # trapezoid between planes q and q + 1
+            path += 0.5 * (nidx[q] + nidx[q + 1])
+        u = amp * np.exp(1j * k0h * path)
+        f[3, z] = u.real
+        f[4, z] = u.imag
+    return f
 
 
 def conv(x, w, b, relu=True):

@@ -28,7 +28,7 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_autotune", "usp_canonical_pantograph", "usp_batch_workspace_bytes", "usp_solve_batched",
            "usp_autotune_batched", "usp_nn_conv3d", "usp_nn_wgrad_workspace", "usp_nn_conv3d_wgrad",
            "usp_nn_pool2", "usp_nn_upsample2", "usp_nn_channel_copy", "usp_nn_relu_backward", "usp_nn_add",
-           "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_transpose_weights", "usp_nn_to_bf16",
+           "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_pack_weights", "usp_nn_to_bf16",
            "usp_nn_pred_to_field"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
@@ -108,10 +108,10 @@ def lib():
     L.usp_nn_channel_copy.argtypes = [P, I, I, P, I, I, I, LG, P]
     L.usp_nn_relu_backward.argtypes = [P, P, P, LG, I, P]
     L.usp_nn_add.argtypes = [P, P, LG, P]
-    L.usp_nn_features.argtypes = [P, P, I, I, I, D, D, D, I, P]
+    L.usp_nn_features.argtypes = [P, P, I, I, I, D, D, D, I, D, D, P]
     L.usp_nn_loss.argtypes = [P, P, F, LG, P, P, DP, P]
     L.usp_nn_adam.argtypes = [P, P, P, P, P, LG, F, F, F, F, I, P]
-    L.usp_nn_transpose_weights.argtypes = [P, P, I, I, I, P]
+    L.usp_nn_pack_weights.argtypes = [P, P, I, I, I, I, P]
     L.usp_nn_to_bf16.argtypes = [P, P, LG, P]
     L.usp_nn_pred_to_field.argtypes = [P, F, P, LG, P]
     L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,

@@ -44,40 +44,77 @@ bool with_conv_shape(int cin, int cout, int taps, F&& f) {
   return false;
 }
 
-long wgrad_chunk(long V) {
-  long c = std::max<long>(256, V * 27 / 2048);
-  return (c + 15) / 16 * 16;
+// Row chunking of the weight gradient: about 4096 waves, partials within 128 MiB.
+struct WgradSplit {
+  int rows_per_chunk, nchunks, tg;
+};
+WgradSplit wgrad_split(int D, int H, int cin, int cout, int taps) {
+  const int tg = wgrad_tg(cin, cout, taps);
+  const int ng = taps / tg;
+  const long R = (long)D * H;
+  long nch = std::min<long>(R, std::max<long>(1, (4096 + ng - 1) / ng));
+  long rpc = (R + nch - 1) / nch;
+  nch = (R + rpc - 1) / rpc;
+  while (nch > 1 && nch * taps * (long)cout * cin * 4 > (128l << 20)) {
+    rpc *= 2;
+    nch = (R + rpc - 1) / rpc;
+  }
+  return {(int)rpc, (int)nch, tg};
 }
+
+constexpr long kBiasChunk = 4096;
+
+bool planes_ok(int c) { return c > 0 && c % 16 == 0; }
 
 }  // namespace
 
 extern "C" {
 
-int usp_nn_conv3d(const void* in, const void* w, const float* bias, void* out, int out_f32, int cstore, int D, int H,
-                  int W, int cin, int cout, int taps, int sign, int relu, void* stream) {
-  if (!in || !w || !out || D < 1 || H < 1 || W < 1 || cstore < 1 || cstore > cout || (sign != 1 && sign != -1))
+int usp_nn_pack_weights(const void* w, void* packed, int cout, int taps, int cin, int transposed, void* stream) {
+  if (!w || !packed || !planes_ok(cin) || !planes_ok(cout) || (taps != 1 && taps != 27))
     return fail(USP_ERR_INVALID, "invalid argument");
+  hipLaunchKernelGGL(k_wpack, dim3(grid_for((long)cout * taps * cin)), dim3(256), 0, (hipStream_t)stream,
+                     (const uint16_t*)w, (uint16_t*)packed, cout, taps, cin, transposed ? 1 : 0);
+  LAUNCHCHK("k_wpack");
+  return 0;
+}
+
+int usp_nn_conv3d(const void* in, const void* wpk, const float* bias, void* out, int out_f32, int cstore, int D, int H,
+                  int W, int cin, int cout, int taps, int sign, int relu, void* stream) {
+  if (!in || !wpk || !out || D < 1 || H < 1 || W < 1 || cstore < 1 || cstore > cout || (sign != 1 && sign != -1))
+    return fail(USP_ERR_INVALID, "invalid argument");
+  if (!out_f32 && cstore != cout) return fail(USP_ERR_INVALID, "bf16 output keeps every output channel");
   const long V = (long)D * H * W;
-  if (V % 16) return fail(USP_ERR_UNSUPPORTED_SHAPE, "the voxel count must be a multiple of 16");
+  if (V % 16 || V > (1l << 30)) return fail(USP_ERR_UNSUPPORTED_SHAPE, "the voxel count must be a multiple of 16");
   if (sign < 0 && relu) return fail(USP_ERR_INVALID, "the input-gradient convolution takes no ReLU");
-  const int blocks = (int)((V / 16 + 3) / 4);
+  const bool wide = V >= (1l << 18);  // 4 voxel tiles per wave on the large grids
+  const int per_block = wide ? 256 : 64;
+  const int blocks = (int)((V + per_block - 1) / per_block);
   hipStream_t st = (hipStream_t)stream;
   uint16_t* ob = out_f32 ? nullptr : (uint16_t*)out;
   float* of = out_f32 ? (float*)out : nullptr;
-  const uint16_t *ip = (const uint16_t*)in, *wp = (const uint16_t*)w;
+  const uint16_t* ip = (const uint16_t*)in;
+  const uint2* wp = (const uint2*)wpk;
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
-    if (sign > 0) {
-      if (relu)
-        hipLaunchKernelGGL((k_conv<ci, co, tp, 1, true>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of, cstore,
-                           D, H, W);
-      else
-        hipLaunchKernelGGL((k_conv<ci, co, tp, 1, false>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
+    auto go = [&](auto MVc) {
+      constexpr int mv = decltype(MVc)::value;
+      if (sign > 0) {
+        if (relu)
+          hipLaunchKernelGGL((k_conv<ci, co, tp, 1, true, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
+                             cstore, D, H, W);
+        else
+          hipLaunchKernelGGL((k_conv<ci, co, tp, 1, false, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
+                             cstore, D, H, W);
+      } else {
+        hipLaunchKernelGGL((k_conv<ci, co, tp, -1, false, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
                            cstore, D, H, W);
-    } else {
-      hipLaunchKernelGGL((k_conv<ci, co, tp, -1, false>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of, cstore,
-                         D, H, W);
-    }
+      }
+    };
+    if (wide)
+      go(std::integral_constant<int, 4>{});
+    else
+      go(std::integral_constant<int, 1>{});
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
   LAUNCHCHK("k_conv");
@@ -85,12 +122,12 @@ int usp_nn_conv3d(const void* in, const void* w, const float* bias, void* out, i
 }
 
 int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, size_t* bytes) {
-  if (!bytes) return fail(USP_ERR_INVALID, "bytes is NULL");
+  if (!bytes || D < 1 || H < 1 || W < 1 || !planes_ok(cin) || !planes_ok(cout) || (taps != 1 && taps != 27))
+    return fail(USP_ERR_INVALID, "invalid argument");
   const long V = (long)D * H * W;
-  const long chunk = wgrad_chunk(V);
-  const long nch = (V + chunk - 1) / chunk;
-  const long bch = (V + 4095) / 4096;
-  *bytes = sizeof(float) * (nch * taps * (long)cout * cin + bch * (long)cout) + 256;
+  const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
+  const long bch = (V + kBiasChunk - 1) / kBiasChunk;
+  *bytes = sizeof(float) * ((long)sp.nchunks * taps * (long)cout * cin + bch * (long)cout) + 256;
   return 0;
 }
 
@@ -98,26 +135,28 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
                         int W, int cin, int cout, int taps, void* stream) {
   if (!in || !g || !dw || !ws) return fail(USP_ERR_INVALID, "invalid argument");
   size_t need = 0;
-  usp_nn_wgrad_workspace(D, H, W, cin, cout, taps, &need);
+  if (usp_nn_wgrad_workspace(D, H, W, cin, cout, taps, &need)) return USP_ERR_INVALID;
   if (ws_bytes < need) return fail(USP_ERR_WORKSPACE, "wgrad workspace too small");
   const long V = (long)D * H * W;
-  const long chunk = wgrad_chunk(V);
-  const int nch = (int)((V + chunk - 1) / chunk);
+  const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
   hipStream_t st = (hipStream_t)stream;
   float* part = (float*)ws;
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
-    const long items = (long)nch * tp * (co / 16) * (ci / 16);
-    hipLaunchKernelGGL((k_wgrad<ci, co, tp>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st,
-                       (const uint16_t*)in, (const uint16_t*)g, part, (int)chunk, nch, D, H, W);
+    constexpr int tg = wgrad_tg(ci, co, tp);
+    const long items = (long)sp.nchunks * (tp / tg);
+    hipLaunchKernelGGL((k_wgrad<ci, co, tp, tg>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st,
+                       (const uint16_t*)in, (const uint16_t*)g, part, sp.rows_per_chunk, sp.nchunks, D, H, W);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_for((long)taps * cout * cin)), dim3(256), 0, st, part, dw, nch, taps,
+  const long n = (long)taps * cout * cin;
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, dw, sp.nchunks, taps,
                      cout, cin);
   if (db) {
-    float* bpart = part + (long)nch * taps * cout * cin;
-    const int bch = (int)((V + 4095) / 4096);
-    hipLaunchKernelGGL(k_bgrad, dim3(bch), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout, 4096);
+    float* bpart = part + (long)sp.nchunks * taps * cout * cin;
+    const int bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
+    hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
+                       (int)kBiasChunk);
     hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(256), 0, st, bpart, db, bch, cout);
   }
   LAUNCHCHK("k_wgrad");
@@ -125,13 +164,14 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
 }
 
 int usp_nn_pool2(const void* in, void* out, int D, int H, int W, int C, int backward, void* stream) {
-  if (!in || !out || (D | H | W) & 1) return fail(USP_ERR_INVALID, "even grid sizes required");
+  if (!in || !out || (D | H | W) & 1 || !planes_ok(C)) return fail(USP_ERR_INVALID, "invalid argument");
   hipStream_t st = (hipStream_t)stream;
+  const long V = (long)D * H * W;
   if (!backward)
-    hipLaunchKernelGGL(k_pool2, dim3(grid_for((long)D * H * W * C / 8)), dim3(256), 0, st, (const uint16_t*)in,
+    hipLaunchKernelGGL(k_pool2, dim3(grid_for(V / 8 * (C / 16) * 2)), dim3(256), 0, st, (const uint16_t*)in,
                        (uint16_t*)out, D, H, W, C);
   else  // in = gradient on the coarse grid, out = gradient on the fine grid
-    hipLaunchKernelGGL(k_pool2_back, dim3(grid_for((long)D * H * W * C)), dim3(256), 0, st, (const uint16_t*)in,
+    hipLaunchKernelGGL(k_pool2_back, dim3(grid_for(V * (C / 16) * 2)), dim3(256), 0, st, (const uint16_t*)in,
                        (uint16_t*)out, D, H, W, C);
   LAUNCHCHK("k_pool2");
   return 0;
@@ -139,23 +179,27 @@ int usp_nn_pool2(const void* in, void* out, int D, int H, int W, int C, int back
 
 int usp_nn_upsample2(const void* in, void* out, int D, int H, int W, int C, int Ctot, int c0, int backward,
                      void* stream) {
-  if (!in || !out || (D | H | W) & 1 || c0 < 0 || c0 + C > Ctot) return fail(USP_ERR_INVALID, "invalid argument");
+  if (!in || !out || (D | H | W) & 1 || c0 < 0 || c0 + C > Ctot || !planes_ok(C) || c0 % 16)
+    return fail(USP_ERR_INVALID, "invalid argument");
   hipStream_t st = (hipStream_t)stream;
+  const long V = (long)D * H * W;
   if (!backward)
-    hipLaunchKernelGGL(k_up2, dim3(grid_for((long)D * H * W * C)), dim3(256), 0, st, (const uint16_t*)in,
-                       (uint16_t*)out, D, H, W, C, Ctot, c0);
+    hipLaunchKernelGGL(k_up2, dim3(grid_for(V * (C / 16) * 2)), dim3(256), 0, st, (const uint16_t*)in, (uint16_t*)out,
+                       D, H, W, C, c0);
   else  // in = gradient of the fine concatenated tensor, out = coarse gradient
-    hipLaunchKernelGGL(k_up2_back, dim3(grid_for((long)D * H * W * C / 8)), dim3(256), 0, st, (const uint16_t*)in,
-                       (uint16_t*)out, D, H, W, C, Ctot, c0);
+    hipLaunchKernelGGL(k_up2_back, dim3(grid_for(V / 8 * (C / 16) * 2)), dim3(256), 0, st, (const uint16_t*)in,
+                       (uint16_t*)out, D, H, W, C, c0);
   LAUNCHCHK("k_up2");
   return 0;
 }
 
 int usp_nn_channel_copy(const void* src, int Cs, int s0, void* dst, int Cd, int d0, int C, long V, void* stream) {
-  if (!src || !dst || s0 + C > Cs || d0 + C > Cd) return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_chcopy, dim3(grid_for(V * C)), dim3(256), 0, (hipStream_t)stream, (const uint16_t*)src, Cs, s0,
-                     (uint16_t*)dst, Cd, d0, C, V);
-  LAUNCHCHK("k_chcopy");
+  if (!src || !dst || s0 < 0 || d0 < 0 || s0 + C > Cs || d0 + C > Cd || !planes_ok(C) || s0 % 16 || d0 % 16)
+    return fail(USP_ERR_INVALID, "invalid argument");
+  const long n8 = V * C / 8;
+  hipLaunchKernelGGL(k_copy8, dim3(grid_for(n8)), dim3(256), 0, (hipStream_t)stream,
+                     (const uint4*)((const uint16_t*)src + (long)s0 * V), (uint4*)((uint16_t*)dst + (long)d0 * V), n8);
+  LAUNCHCHK("k_copy8");
   return 0;
 }
 
@@ -176,10 +220,12 @@ int usp_nn_add(void* dst, const void* src, long n, void* stream) {
 }
 
 int usp_nn_features(const void* nidx, void* out, int D, int H, int W, double n_bg, double n_span, double kappa_max,
-                    int plane, void* stream) {
-  if (!nidx || !out || !(n_span > 0.0) || !(kappa_max > 0.0)) return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_features, dim3(grid_for((long)D * H * W)), dim3(256), 0, (hipStream_t)stream,
-                     (const float2*)nidx, (uint16_t*)out, D, H, W, n_bg, n_span, kappa_max, plane);
+                    int plane, double k0h, double w0, void* stream) {
+  if (!nidx || !out || D < 1 || H < 1 || W < 1 || plane < 0 || plane >= D || !(n_span > 0.0) || !(kappa_max > 0.0) ||
+      !(w0 > 0.0))
+    return fail(USP_ERR_INVALID, "invalid argument");
+  hipLaunchKernelGGL(k_features, dim3(grid_for((long)H * W)), dim3(256), 0, (hipStream_t)stream, (const float2*)nidx,
+                     (uint16_t*)out, D, H, W, n_bg, n_span, kappa_max, plane, k0h, w0);
   LAUNCHCHK("k_features");
   return 0;
 }
@@ -192,7 +238,7 @@ int usp_nn_loss(const float* pred, const void* target, float scale, long V, void
   double* part = (double*)ws;
   double* res = part + 2 * nb;
   hipLaunchKernelGGL(k_loss_parts, dim3(nb), dim3(256), 0, st, pred, (const float2*)target, scale, V, part);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, part, nb, res);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, part, nb, res);
   if (grad)
     hipLaunchKernelGGL(k_loss_grad, dim3(grid_for(V)), dim3(256), 0, st, pred, (const float2*)target, scale, V, res,
                        (uint16_t*)grad);
@@ -209,14 +255,6 @@ int usp_nn_adam(float* w, const float* g, float* m, float* v, void* wb, long n, 
   hipLaunchKernelGGL(k_adam, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, w, g, m, v, (uint16_t*)wb, n, lr,
                      b1, b2, eps, c1, c2);
   LAUNCHCHK("k_adam");
-  return 0;
-}
-
-int usp_nn_transpose_weights(const void* w, void* wt, int cout, int taps, int cin, void* stream) {
-  if (!w || !wt) return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_wtrans, dim3(grid_for((long)cout * taps * cin)), dim3(256), 0, (hipStream_t)stream,
-                     (const uint16_t*)w, (uint16_t*)wt, cout, taps, cin);
-  LAUNCHCHK("k_wtrans");
   return 0;
 }
 

@@ -1,13 +1,21 @@
 // Kernels of the learned initial guess: a small 3-D convolutional network on
-// channels-last bf16 activations with fp32 accumulation on the matrix cores.
+// bf16 activations with fp32 accumulation on the matrix cores.
 //
-// Tensors: activations [V][C] bf16 (stored as raw 16-bit words), V = D*H*W
-// voxels with x fastest, C a multiple of 16; conv weights [COUT][TAPS][CIN]
-// bf16 (fp32 master copy in the same layout); biases fp32 [COUT].  A 3x3x3
-// convolution with zero padding is an implicit GEMM
-//     out[v][co] = sum_{tap, ci} in[v + off(tap)][ci] * w[co][tap][ci]
-// computed with v_mfma_f32_16x16x16 bf16 tiles: one wave owns 16 voxels and
-// all output channels.
+// Activation layout: 16-channel planes.  A tensor with C channels (C a
+// multiple of 16) over V = D*H*W voxels (x fastest) is C/16 planes of
+// [V][16] bf16 (raw 16-bit words):
+//     element (v, c) at  ((c / 16) * V + v) * 16 + c % 16
+// so the 16 x 16 (voxel x channel) operand of one v_mfma_f32_16x16x16 bf16
+// is 512 contiguous bytes for 16 consecutive voxels, and concatenating
+// tensors along channels is placing their planes one after the other.
+// Conv weights [COUT][TAPS][CIN] bf16 (fp32 master copy in the same layout)
+// are repacked into fragment order for the kernels (k_wpack); biases fp32.
+//
+// A 3x3x3 convolution with zero padding is an implicit GEMM
+//     out[v][co] = sum_{tap, ci} in[v + off(tap)][ci] * w[co][tap][ci].
+// Operand lane layout of v_mfma_f32_16x16x16 bf16 (A 16x16, B 16x16, D = A B):
+// lane l holds A[l % 16][4 (l / 16) + e] and B[4 (l / 16) + e][l % 16] for
+// e = 0..3, and D[4 (l / 16) + e][l % 16] in element e of its accumulator.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,8 +34,7 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-__device__ __forceinline__ v4s ld4(const uint16_t* p) {
-  const uint2 q = *reinterpret_cast<const uint2*>(p);
+__device__ __forceinline__ v4s as_v4s(uint2 q) {
   v4s r;
   r[0] = (short)(q.x & 0xffff);
   r[1] = (short)(q.x >> 16);
@@ -35,134 +42,237 @@ __device__ __forceinline__ v4s ld4(const uint16_t* p) {
   r[3] = (short)(q.y >> 16);
   return r;
 }
+__device__ __forceinline__ v4s ld4(const uint16_t* p) { return as_v4s(*reinterpret_cast<const uint2*>(p)); }
+
+__device__ __forceinline__ void tap_offsets(int tap, int taps, int& dz, int& dy, int& dx) {
+  dz = dy = dx = 0;
+  if (taps == 27) {
+    dz = tap / 9 - 1;
+    dy = (tap / 3) % 3 - 1;
+    dx = tap % 3 - 1;
+  }
+}
+
+// Weights in fragment order.  For a convolution with CIN input and COUT
+// output channels (KC = CIN/16, NT = COUT/16) the B operand of (tap, kc, t)
+// is 64 lanes x 4 bf16:
+//   pk[((tap * KC + kc) * NT + t) * 64 + l][e] = Wc[t*16 + l%16][tap][kc*16 + 4 (l/16) + e]
+// with Wc = w (forward, w is [COUT][TAPS][CIN]) or, for the input gradient,
+// Wc[a][tap][b] = w[b][tap][a] (w is then the forward layer's [CIN][TAPS][COUT]
+// weights seen from the other side: here cin/cout are the forward layer's).
+__global__ void k_wpack(const uint16_t* __restrict__ w, uint16_t* __restrict__ pk, int cout, int taps, int cin,
+                        int transposed) {
+  const int ci_c = transposed ? cout : cin;   // input channels of the packed convolution
+  const int co_c = transposed ? cin : cout;   // its output channels
+  const int KC = ci_c / 16, NT = co_c / 16;
+  const long n = (long)taps * ci_c * co_c;
+  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+    const int e = (int)(j & 3), l = (int)((j >> 2) & 63);
+    const long rest = j >> 8;
+    const int t = (int)(rest % NT), kc = (int)((rest / NT) % KC), tap = (int)(rest / ((long)NT * KC));
+    const int a = t * 16 + (l & 15), b = kc * 16 + 4 * (l >> 4) + e;   // Wc[a][tap][b]
+    pk[j] = transposed ? w[((long)b * taps + tap) * cin + a] : w[((long)a * taps + tap) * cin + b];
+  }
+}
 
 // Implicit-GEMM convolution.  TAPS = 27 (3x3x3, padding 1) or 1 (1x1x1).
-// SIGN = +1: forward (neighbour v + off); SIGN = -1 with the weight layout
-// [CIN_fwd][TAPS][COUT_fwd] gives the gradient with respect to the input.
-// The first `cstore` output channels are written with row pitch `cstore`
-// (bf16, or fp32 when out_f32), after bias and optional ReLU.
-template <int CIN, int COUT, int TAPS, int SIGN, bool RELU>
+// SIGN = +1: forward (neighbour v + off); SIGN = -1 with transposed packing
+// gives the gradient with respect to the input.  One wave computes MV tiles
+// of 16 consecutive voxels x all COUT channels, so every weight fragment
+// feeds MV matrix-core products and every activation operand NT of them.
+// Output: bf16 planes (all COUT channels), or fp32 rows [V][cstore] of the
+// first cstore channels when out_f32; bias and ReLU applied first.
+template <int CIN, int COUT, int TAPS, int SIGN, bool RELU, int MV>
 __global__ void __launch_bounds__(256)
-k_conv(const uint16_t* __restrict__ in, const uint16_t* __restrict__ w, const float* __restrict__ bias,
+k_conv(const uint16_t* __restrict__ in, const uint2* __restrict__ wpk, const float* __restrict__ bias,
        uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore, int D, int H, int W) {
   constexpr int NT = COUT / 16, KC = CIN / 16;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long V = (long)D * H * W;
-  const long v0 = ((long)blockIdx.x * 4 + wave) * 16;
-  if (v0 >= V) return;  // whole wave; the kernel has no block barrier
+  const int V = D * H * W;
+  const int vw = (blockIdx.x * 4 + wave) * (16 * MV);
+  if (vw >= V) return;  // whole wave; the kernel has no block barrier
   const int i = lane & 15, kq = lane >> 4;
-  const long v = v0 + i;
-  const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long)W * H));
-  v4f acc[NT];
+  int xm[MV], ym[MV], zm[MV];
+  bool live[MV];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < MV; ++m) {
+    const int v = vw + 16 * m + i;
+    live[m] = vw + 16 * m < V;  // V is a multiple of 16: tiles are whole
+    xm[m] = v % W;
+    ym[m] = (v / W) % H;
+    zm[m] = v / (W * H);
+  }
+  v4f acc[MV][NT];
+#pragma unroll
+  for (int m = 0; m < MV; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int tap = 0; tap < TAPS; ++tap) {
-    int dz = 0, dy = 0, dx = 0;
-    if (TAPS == 27) {
-      dz = tap / 9 - 1;
-      dy = (tap / 3) % 3 - 1;
-      dx = tap % 3 - 1;
+    int dz, dy, dx;
+    tap_offsets(tap, TAPS, dz, dy, dx);
+    int nb[MV];
+    bool ok[MV];
+#pragma unroll
+    for (int m = 0; m < MV; ++m) {
+      const int zz = zm[m] + SIGN * dz, yy = ym[m] + SIGN * dy, xx = xm[m] + SIGN * dx;
+      ok[m] = live[m] && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      nb[m] = (zz * H + yy) * W + xx;
     }
-    const int zz = z + SIGN * dz, yy = y + SIGN * dy, xx = x + SIGN * dx;
-    const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const long nb = ((long)zz * H + yy) * W + xx;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
-      const v4s a = ok ? ld4(in + nb * CIN + kc * 16 + 4 * kq) : v4s{0, 0, 0, 0};
+      v4s b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const v4s b = ld4(w + ((long)(t * 16 + i) * TAPS + tap) * CIN + kc * 16 + 4 * kq);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+      for (int t = 0; t < NT; ++t) b[t] = as_v4s(wpk[((tap * KC + kc) * NT + t) * 64 + lane]);
+#pragma unroll
+      for (int m = 0; m < MV; ++m) {
+        const v4s a = ok[m] ? ld4(in + ((long)kc * V + nb[m]) * 16 + 4 * kq) : v4s{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
       }
     }
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int co = t * 16 + i;
-    if (co >= cstore) continue;
     const float bb = bias ? bias[co] : 0.f;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      float val = acc[t][e] + bb;
-      if (RELU) val = fmaxf(val, 0.f);
-      const long o = (v0 + 4 * kq + e) * cstore + co;
-      if (out_f32) out_f32[o] = val;
-      else out_bf[o] = f2bf(val);
+    for (int m = 0; m < MV; ++m) {
+      if (!live[m]) continue;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        float val = acc[m][t][e] + bb;
+        if (RELU) val = fmaxf(val, 0.f);
+        const long v = vw + 16 * m + 4 * kq + e;
+        if (out_f32) {
+          if (co < cstore) out_f32[v * cstore + co] = val;
+        } else {
+          out_bf[((long)t * V + v) * 16 + i] = f2bf(val);
+        }
+      }
     }
   }
 }
 
-// Weight gradient partials.  Work item = (voxel chunk c, tap, (co-tile,
-// ci-tile) pair), one per wave:
-//   part[c][tap][co][ci] = sum_{v in chunk c} in[v + off(tap)][ci] * g[v][co]
-// (a GEMM over voxels: A = g^T (co x v), B = shifted input (v x ci)).
-template <int CIN, int COUT, int TAPS>
+// Taps per wave in the weight gradient: the gradient operand (unshifted) is
+// loaded once and used for TG taps; TG * (COUT/16) * (CIN/16) accumulator
+// tiles stay within 36.
+__host__ __device__ constexpr int wgrad_tg(int cin, int cout, int taps) {
+  return taps == 1 ? 1
+                   : ((cin / 16) * (cout / 16) * 27 <= 36 ? 27
+                                                          : ((cin / 16) * (cout / 16) * 9 <= 36
+                                                                 ? 9
+                                                                 : ((cin / 16) * (cout / 16) * 3 <= 36 ? 3 : 1)));
+}
+
+// Weight gradient partials.  Wave work item = (row chunk c, tap group): the
+// wave sums over the rows (z, y) of its chunk and every x,
+//   part[c][tap][co][ci] = sum g[z,y,x][co] * in[z+dz, y+dy, x+dx][ci]
+// for the TG taps of its group and every (co, ci) tile: a GEMM over voxels
+// with A = g^T (co x voxel) and B = the shifted input (voxel x ci).  Rows whose
+// shifted row lies outside the grid contribute nothing and are skipped.
+template <int CIN, int COUT, int TAPS, int TG>
 __global__ void __launch_bounds__(256)
-k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g, float* __restrict__ part, int chunk,
+k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g, float* __restrict__ part, int rows_per_chunk,
         int nchunks, int D, int H, int W) {
-  constexpr int MT = COUT / 16, NTl = CIN / 16, PAIRS = MT * NTl;
+  constexpr int MT = COUT / 16, NTl = CIN / 16, NG = TAPS / TG;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int i = lane & 15, kq = lane >> 4;
   const long V = (long)D * H * W;
-  const long item = (long)blockIdx.x * 4 + wave;
-  if (item >= (long)nchunks * TAPS * PAIRS) return;  // whole wave; no block barrier in this kernel
-  const int pair = (int)(item % PAIRS);
-  const int tap = (int)((item / PAIRS) % TAPS);
-  const long c = item / ((long)PAIRS * TAPS);
-  const int mt = pair / NTl, nt = pair % NTl;
-  int dz = 0, dy = 0, dx = 0;
-  if (TAPS == 27) {
-    dz = tap / 9 - 1;
-    dy = (tap / 3) % 3 - 1;
-    dx = tap % 3 - 1;
-  }
-  const long c0 = c * chunk;
-  const long c1 = (c0 + chunk < V) ? c0 + chunk : V;
-  v4f acc = {0.f, 0.f, 0.f, 0.f};
-  for (long vs = c0; vs < c1; vs += 16) {
-    v4s a, b;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= nchunks * NG) return;  // whole wave; no block barrier in this kernel
+  const int grp = item % NG, c = item / NG;
+  const int r0 = c * rows_per_chunk;
+  const int r1 = min(r0 + rows_per_chunk, D * H);
+  v4f acc[TG][MT][NTl];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const long v = vs + 4 * kq + e;
-      short av = 0, bv = 0;
-      if (v < c1) {
-        av = (short)g[v * COUT + mt * 16 + i];
-        const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long)W * H));
-        const int zz = z + dz, yy = y + dy, xx = x + dx;
-        if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-          bv = (short)in[(((long)zz * H + yy) * W + xx) * CIN + nt * 16 + i];
+  for (int t = 0; t < TG; ++t)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTl; ++nt) acc[t][mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int r = r0; r < r1; ++r) {
+    const int z = r / H, y = r - (r / H) * H;
+    for (int xs = 0; xs < W; xs += 16) {
+      const int xl = xs + 4 * kq;  // this lane's voxels are x = xl .. xl + 3 of row r
+      v4s a[MT];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          a[mt][e] = (xl + e < W) ? (short)g[((long)mt * V + (long)r * W + xl + e) * 16 + i] : (short)0;
+#pragma unroll
+      for (int t = 0; t < TG; ++t) {
+        int dz, dy, dx;
+        tap_offsets(grp * TG + t, TAPS, dz, dy, dx);
+        const int zz = z + dz, yy = y + dy;
+        if (zz < 0 || zz >= D || yy < 0 || yy >= H) continue;  // uniform across the wave
+        const long sb = ((long)zz * H + yy) * W;
+#pragma unroll
+        for (int nt = 0; nt < NTl; ++nt) {
+          v4s b;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int x = xl + e + dx;
+            b[e] = (xl + e < W && x >= 0 && x < W) ? (short)in[((long)nt * V + sb + x) * 16 + i] : (short)0;
+          }
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt)
+            acc[t][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[mt], b, acc[t][mt][nt], 0, 0, 0);
+        }
       }
-      a[e] = av;
-      b[e] = bv;
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
   }
-  // lane holds C[co = mt*16 + 4 kq + e][ci = nt*16 + i]
-  float* dst = part + (c * TAPS + tap) * (long)COUT * CIN;
+  // lane holds D[co = mt*16 + 4 kq + e][ci = nt*16 + i]
 #pragma unroll
-  for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * kq + e) * CIN + nt * 16 + i] = acc[e];
-}
-
-// out[j] = sum_c part[c][j] over nchunks (fixed order), written to the
-// [COUT][TAPS][CIN] gradient layout from the [chunk][TAPS][COUT][CIN] partials.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int nchunks, int taps, int cout,
-                               int cin) {
-  const long n = (long)taps * cout * cin;
-  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(long)c * n + j];
-    const int tap = (int)(j / ((long)cout * cin)), co = (int)((j / cin) % cout), ci = (int)(j % cin);
-    dw[((long)co * taps + tap) * cin + ci] = s;
+  for (int t = 0; t < TG; ++t) {
+    float* dst = part + ((long)c * TAPS + grp * TG + t) * (long)COUT * CIN;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NTl; ++nt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * kq + e) * CIN + nt * 16 + i] = acc[t][mt][nt][e];
   }
 }
 
-// bias gradient partials: part[block][co] = sum over the block's voxels of g[v][co]
-__global__ void k_bgrad(const uint16_t* __restrict__ g, float* __restrict__ part, long V, int C, int chunk) {
+// dw[co][tap][ci] = sum over chunks c (in increasing order within each of 16
+// interleaved lanes, then the 16 lane sums in order) of part[c][tap][co][ci].
+__global__ void __launch_bounds__(1024)
+k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int nchunks, int taps, int cout, int cin) {
+  __shared__ float sh[16][65];
+  const long n = (long)taps * cout * cin;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const long j = (long)blockIdx.x * 64 + tx;
+  float s = 0.f;
+  if (j < n)
+    for (int c = ty; c < nchunks; c += 16) s += part[(long)c * n + j];
+  sh[ty][tx] = s;
+  __syncthreads();
+  if (ty == 0 && j < n) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += sh[q][tx];
+    const int tap = (int)(j / ((long)cout * cin)), co = (int)((j / cin) % cout), ci = (int)(j % cin);
+    dw[((long)co * taps + tap) * cin + ci] = t;
+  }
+}
+
+// Bias gradient partials: part[b][p*16 + c] = sum over the chunk's voxels of
+// g(v, p*16 + c); grid (chunks, planes), 256 threads = 16 voxel lanes x 16
+// channels, lane sums combined in order.
+__global__ void __launch_bounds__(256)
+k_bgrad(const uint16_t* __restrict__ g, float* __restrict__ part, long V, int C, int chunk) {
+  __shared__ float sh[16][17];
+  const int c = threadIdx.x & 15, vl = threadIdx.x >> 4, p = blockIdx.y;
   const long v0 = (long)blockIdx.x * chunk;
-  for (int co = threadIdx.x; co < C; co += blockDim.x) {
-    float s = 0.f;
-    for (long v = v0; v < v0 + chunk && v < V; ++v) s += bf2f(g[v * C + co]);
-    part[(long)blockIdx.x * C + co] = s;
+  const long v1 = v0 + chunk < V ? v0 + chunk : V;
+  float s = 0.f;
+  for (long v = v0 + vl; v < v1; v += 16) s += bf2f(g[((long)p * V + v) * 16 + c]);
+  sh[vl][c] = s;
+  __syncthreads();
+  if (vl == 0) {
+    float t = 0.f;
+    for (int q = 0; q < 16; ++q) t += sh[q][c];
+    part[(long)blockIdx.x * C + p * 16 + c] = t;
   }
 }
 __global__ void k_bgrad_reduce(const float* __restrict__ part, float* __restrict__ db, int nchunks, int C) {
@@ -173,75 +283,111 @@ __global__ void k_bgrad_reduce(const float* __restrict__ part, float* __restrict
   }
 }
 
-// 2x2x2 average pooling and its gradient; nearest upsampling and its gradient
-// (channels-last bf16, the coarse grid has D/2 x H/2 x W/2 voxels)
+// ---- pooling, upsampling, copies: 8 channels (16 bytes) per thread ----------
+__device__ __forceinline__ void unpack8(uint4 q, float* f) {
+  const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    f[2 * k] = __uint_as_float(w[k] << 16);
+    f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+  }
+}
+__device__ __forceinline__ uint4 pack8(const float* f) {
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// 2x2x2 average pooling (fine D x H x W -> coarse), per plane.
 __global__ void k_pool2(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int D, int H, int W, int C) {
   const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-  const long n = (long)Do * Ho * Wo * C;
+  const long V = (long)D * H * W, Vo = (long)Do * Ho * Wo;
+  const long n = (C / 16) * Vo * 2;
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(j % C);
-    const long vo = j / C;
+    const int half = (int)(j & 1);
+    const long r = j >> 1;
+    const long vo = r % Vo;
+    const int p = (int)(r / Vo);
     const int xo = (int)(vo % Wo), yo = (int)((vo / Wo) % Ho), zo = (int)(vo / ((long)Wo * Ho));
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int d = 0; d < 8; ++d) {
       const long vi = ((long)(2 * zo + (d >> 2)) * H + (2 * yo + ((d >> 1) & 1))) * W + (2 * xo + (d & 1));
-      s += bf2f(in[vi * C + c]);
+      float f[8];
+      unpack8(*reinterpret_cast<const uint4*>(in + ((long)p * V + vi) * 16 + 8 * half), f);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += f[k];
     }
-    out[j] = f2bf(0.125f * s);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] *= 0.125f;
+    *reinterpret_cast<uint4*>(out + ((long)p * Vo + vo) * 16 + 8 * half) = pack8(s);
   }
 }
+// gradient of k_pool2: fine = coarse parent / 8
 __global__ void k_pool2_back(const uint16_t* __restrict__ gout, uint16_t* __restrict__ gin, int D, int H, int W,
                              int C) {
-  const long n = (long)D * H * W * C;
   const int Ho = H / 2, Wo = W / 2;
+  const long V = (long)D * H * W, Vo = (long)(D / 2) * Ho * Wo;
+  const long n = (C / 16) * V * 2;
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(j % C);
-    const long v = j / C;
+    const int half = (int)(j & 1);
+    const long r = j >> 1;
+    const long v = r % V;
+    const int p = (int)(r / V);
     const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long)W * H));
     const long vo = ((long)(z / 2) * Ho + y / 2) * Wo + x / 2;
-    gin[j] = f2bf(0.125f * bf2f(gout[vo * C + c]));
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(gout + ((long)p * Vo + vo) * 16 + 8 * half), f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) f[k] *= 0.125f;
+    *reinterpret_cast<uint4*>(gin + ((long)p * V + v) * 16 + 8 * half) = pack8(f);
   }
 }
-// out (fine grid D x H x W) = in (coarse) at (z/2, y/2, x/2), written into
-// channels [c0, c0 + C) of an output with Ctot channels
-__global__ void k_up2(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int D, int H, int W, int C,
-                      int Ctot, int c0) {
-  const long n = (long)D * H * W * C;
+// Nearest upsampling: out (fine grid D x H x W, planes c0/16 ..) = in (coarse,
+// C channels) at (z/2, y/2, x/2).
+__global__ void k_up2(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int D, int H, int W, int C, int c0) {
   const int Ho = H / 2, Wo = W / 2;
+  const long V = (long)D * H * W, Vo = (long)(D / 2) * Ho * Wo;
+  const long n = (C / 16) * V * 2;
+  const int p0 = c0 / 16;
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(j % C);
-    const long v = j / C;
+    const int half = (int)(j & 1);
+    const long r = j >> 1;
+    const long v = r % V;
+    const int p = (int)(r / V);
     const int x = (int)(v % W), y = (int)((v / W) % H), z = (int)(v / ((long)W * H));
     const long vo = ((long)(z / 2) * Ho + y / 2) * Wo + x / 2;
-    out[v * Ctot + c0 + c] = in[vo * C + c];
+    *reinterpret_cast<uint4*>(out + ((long)(p0 + p) * V + v) * 16 + 8 * half) =
+        *reinterpret_cast<const uint4*>(in + ((long)p * Vo + vo) * 16 + 8 * half);
   }
 }
-// gradient of k_up2: coarse[vo][c] = sum of the 8 fine children's gradients
+// gradient of k_up2: coarse = sum of the 8 fine children (planes c0/16 .. of gfine)
 __global__ void k_up2_back(const uint16_t* __restrict__ gfine, uint16_t* __restrict__ gcoarse, int D, int H, int W,
-                           int C, int Ctot, int c0) {
+                           int C, int c0) {
   const int Do = D / 2, Ho = H / 2, Wo = W / 2;
-  const long n = (long)Do * Ho * Wo * C;
+  const long V = (long)D * H * W, Vo = (long)Do * Ho * Wo;
+  const long n = (C / 16) * Vo * 2;
+  const int p0 = c0 / 16;
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int c = (int)(j % C);
-    const long vo = j / C;
+    const int half = (int)(j & 1);
+    const long r = j >> 1;
+    const long vo = r % Vo;
+    const int p = (int)(r / Vo);
     const int xo = (int)(vo % Wo), yo = (int)((vo / Wo) % Ho), zo = (int)(vo / ((long)Wo * Ho));
-    float s = 0.f;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     for (int d = 0; d < 8; ++d) {
       const long vi = ((long)(2 * zo + (d >> 2)) * H + (2 * yo + ((d >> 1) & 1))) * W + (2 * xo + (d & 1));
-      s += bf2f(gfine[vi * Ctot + c0 + c]);
+      float f[8];
+      unpack8(*reinterpret_cast<const uint4*>(gfine + ((long)(p0 + p) * V + vi) * 16 + 8 * half), f);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s[k] += f[k];
     }
-    gcoarse[j] = f2bf(s);
+    *reinterpret_cast<uint4*>(gcoarse + ((long)p * Vo + vo) * 16 + 8 * half) = pack8(s);
   }
 }
-// copy channels: dst[v][d0 + c] = src[v][s0 + c], c < C
-__global__ void k_chcopy(const uint16_t* __restrict__ src, int Cs, int s0, uint16_t* __restrict__ dst, int Cd, int d0,
-                         int C, long V) {
-  const long n = V * C;
-  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const long v = j / C;
-    const int c = (int)(j % C);
-    dst[v * Cd + d0 + c] = src[v * Cs + s0 + c];
-  }
+// contiguous copy of n8 * 8 bf16 (whole planes)
+__global__ void k_copy8(const uint4* __restrict__ src, uint4* __restrict__ dst, long n8) {
+  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n8; j += (long)gridDim.x * blockDim.x) dst[j] = src[j];
 }
 // g_pre = g_post * (y > 0), optionally accumulating into an existing gradient
 __global__ void k_relu_back(const uint16_t* __restrict__ y, const uint16_t* __restrict__ g, uint16_t* __restrict__ out,
@@ -258,27 +404,57 @@ __global__ void k_add_bf(uint16_t* __restrict__ dst, const uint16_t* __restrict_
     dst[j] = f2bf(bf2f(dst[j]) + bf2f(src[j]));
 }
 
-// Network input from the complex refractive index n + i kappa: channel 0
-// (Re n - n_bg)/n_span, channel 1 kappa/kappa_max, channel 2 the source plane
-// indicator (z == plane), channels 3..15 zero.
+// Network input from the complex refractive index n + i kappa (one plane of
+// 16 channels): channel 0 (Re n - n_bg)/n_span, channel 1 kappa/kappa_max,
+// channel 2 the source plane indicator (z == plane), channels 3, 4 the real
+// and imaginary parts of the source's Gaussian beam amp(x, y) =
+// exp(-((x - W/2)^2 + (y - H/2)^2)/w0^2) carried along z with the phase and
+// attenuation of the medium, exp(i k0h sum (n + i kappa)) (trapezoid between
+// neighbouring planes, from the source plane up and down), channels 5..15
+// zero.  One thread per (x, y) column walks z; the path sums are in double.
+__device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane, double amp, double pr, double pi,
+                                            double k0h, double n_bg, double n_span, double kappa_max) {
+  const double a = amp * exp(-k0h * pi);
+  const double ph = fmod(k0h * pr, 6.283185307179586);
+  float f[8] = {(float)((q.x - n_bg) / n_span), (float)(q.y / kappa_max), on_plane ? 1.f : 0.f,
+                (float)(a * cos(ph)), (float)(a * sin(ph)), 0.f, 0.f, 0.f};
+  uint4* w = reinterpret_cast<uint4*>(o);
+  w[0] = pack8(f);
+  w[1] = uint4{0u, 0u, 0u, 0u};
+}
 __global__ void k_features(const float2* __restrict__ nidx, uint16_t* __restrict__ out, int D, int H, int W,
-                           double n_bg, double n_span, double kappa_max, int plane) {
-  const long V = (long)D * H * W;
-  for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < V; v += (long)gridDim.x * blockDim.x) {
-    const int z = (int)(v / ((long)W * H));
-    const float2 q = nidx[v];
-    uint16_t* o = out + v * 16;
-    o[0] = f2bf((float)((q.x - n_bg) / n_span));
-    o[1] = f2bf((float)(q.y / kappa_max));
-    o[2] = f2bf(z == plane ? 1.f : 0.f);
-    for (int c = 3; c < 16; ++c) o[c] = 0;
+                           double n_bg, double n_span, double kappa_max, int plane, double k0h, double w0) {
+  const long cols = (long)H * W;
+  for (long col = blockIdx.x * (long)blockDim.x + threadIdx.x; col < cols; col += (long)gridDim.x * blockDim.x) {
+    const double dx = (double)(col % W) - 0.5 * W, dy = (double)(col / W) - 0.5 * H;
+    const double amp = exp(-(dx * dx + dy * dy) / (w0 * w0));
+    const float2 q0 = nidx[(long)plane * cols + col];
+    feature_row(out + ((long)plane * cols + col) * 16, q0, true, amp, 0.0, 0.0, k0h, n_bg, n_span, kappa_max);
+    double pr = 0.0, pi = 0.0;
+    float2 prev = q0;
+    for (int z = plane + 1; z < D; ++z) {
+      const float2 q = nidx[(long)z * cols + col];
+      pr += 0.5 * ((double)prev.x + q.x);
+      pi += 0.5 * ((double)prev.y + q.y);
+      prev = q;
+      feature_row(out + ((long)z * cols + col) * 16, q, false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
+    }
+    pr = pi = 0.0;
+    prev = q0;
+    for (int z = plane - 1; z >= 0; --z) {
+      const float2 q = nidx[(long)z * cols + col];
+      pr += 0.5 * ((double)prev.x + q.x);
+      pi += 0.5 * ((double)prev.y + q.y);
+      prev = q;
+      feature_row(out + ((long)z * cols + col) * 16, q, false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
+    }
   }
 }
 
 // Relative L2 loss between the prediction p[v][0..1] (fp32, Re/Im scaled by
 // 1/s) and the target field x[v] (complex64): per-block partials of
-// |s p - x|^2 and |x|^2; the gradient g[v][c] (bf16, 16 channels, zero beyond 2)
-// = 2 s (s p - x) / ||x||^2 is written by k_loss_grad once ||x||^2 is known.
+// |s p - x|^2 and |x|^2; the gradient g (one plane of 16 channels, zero beyond
+// 2) = 2 s (s p - x) / ||x||^2 is written by k_loss_grad once ||x||^2 is known.
 __global__ void k_loss_parts(const float* __restrict__ p, const float2* __restrict__ x, float s, long V,
                              double* __restrict__ part) {
   __shared__ double sh[2][256];
@@ -303,25 +479,35 @@ __global__ void k_loss_parts(const float* __restrict__ p, const float2* __restri
     part[2 * blockIdx.x + 1] = sh[1][0];
   }
 }
+// one block of 256: lane sums over blocks q = lane, lane + 256, ..., then in order
 __global__ void k_loss_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double a = 0.0, b = 0.0;
-    for (int i = 0; i < nb; ++i) {
-      a += part[2 * i];
-      b += part[2 * i + 1];
+  __shared__ double sh[2][256];
+  double a = 0.0, b = 0.0;
+  for (int q = threadIdx.x; q < nb; q += blockDim.x) {
+    a += part[2 * q];
+    b += part[2 * q + 1];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int q = 0; q < (int)blockDim.x; ++q) {
+      sa += sh[0][q];
+      sb += sh[1][q];
     }
-    out[0] = a / b;  // relative squared error
-    out[1] = b;
+    out[0] = sa / sb;  // relative squared error
+    out[1] = sb;
   }
 }
 __global__ void k_loss_grad(const float* __restrict__ p, const float2* __restrict__ x, float s, long V,
                             const double* __restrict__ lossv, uint16_t* __restrict__ g) {
   const float scale = (float)(2.0 * s / lossv[1]);
   for (long v = blockIdx.x * (long)blockDim.x + threadIdx.x; v < V; v += (long)gridDim.x * blockDim.x) {
-    uint16_t* o = g + v * 16;
-    o[0] = f2bf(scale * (s * p[2 * v] - x[v].x));
-    o[1] = f2bf(scale * (s * p[2 * v + 1] - x[v].y));
-    for (int c = 2; c < 16; ++c) o[c] = 0;
+    float f[8] = {scale * (s * p[2 * v] - x[v].x), scale * (s * p[2 * v + 1] - x[v].y), 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    uint4* o = reinterpret_cast<uint4*>(g + v * 16);
+    o[0] = pack8(f);
+    o[1] = uint4{0u, 0u, 0u, 0u};
   }
 }
 
@@ -340,16 +526,7 @@ __global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float
   }
 }
 
-// [COUT][TAPS][CIN] -> [CIN][TAPS][COUT] (weights for the input gradient)
-__global__ void k_wtrans(const uint16_t* __restrict__ w, uint16_t* __restrict__ wt, int cout, int taps, int cin) {
-  const long n = (long)cout * taps * cin;
-  for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int ci = (int)(j % cin), tap = (int)((j / cin) % taps), co = (int)(j / ((long)cin * taps));
-    wt[((long)ci * taps + tap) * cout + co] = w[j];
-  }
-}
-
-// fp32 -> bf16 and bf16 -> fp32 conversions
+// fp32 -> bf16
 __global__ void k_f2bf(const float* __restrict__ a, uint16_t* __restrict__ b, long n) {
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) b[j] = f2bf(a[j]);
 }

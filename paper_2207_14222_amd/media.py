@@ -30,7 +30,7 @@ H_WAVE = 0.25               # lambda / 4
 
 __all__ = [
     "HelmholtzProblem", "DiffusionProblem", "PantographProblem",
-    "absorbing_kappa", "helmholtz_1d", "helmholtz_spheres", "helmholtz_disks",
+    "absorbing_kappa", "helmholtz_1d", "helmholtz_spheres", "sphere_index", "beam_source", "helmholtz_disks",
     "helmholtz_homogeneous", "diffusion_blobs", "pantograph", "batch_sizes",
 ]
 
@@ -148,16 +148,26 @@ def _beam_source(shape, plane, w0):
     return src
 
 
+def sphere_index(shape=(256, 256, 256), seed=2, count=200, background=1.33):
+    """Real refractive index of the random-sphere medium (no absorbing layers):
+    background n with ``count`` spheres of radius 2-12 px and n uniform in [1.33, 1.5]."""
+    rng = np.random.default_rng(seed)
+    nre = np.full(shape, background, dtype=np.float64)
+    return _paint_balls(nre, count, rng)
+
+
+def beam_source(shape, plane=20, w0=16.0):
+    """Gaussian-beam source on index ``plane`` of axis 0 (clamped to the grid)."""
+    return _beam_source(shape, min(plane, shape[0] - 1), w0)
+
+
 def helmholtz_spheres(shape=(256, 256, 256), seed=2, count=200, width=16,
                       kappa_max=0.2, w0=16.0, plane=20, background=1.33):
     """3-D medium: background n=1.33 with ``count`` random spheres (radius 2-12 px,
     n uniform in [1.33, 1.5]), absorbing faces, Gaussian-beam source on z = ``plane``."""
-    rng = np.random.default_rng(seed)
-    nre = np.full(shape, background, dtype=np.float64)
-    _paint_balls(nre, count, rng)
+    nre = sphere_index(shape, seed, count, background)
     nidx = nre + 1j * absorbing_kappa(shape, width, kappa_max)
-    plane = min(plane, shape[0] - 1)
-    return HelmholtzProblem(k2=_k2_from_index(nidx), source=_beam_source(shape, plane, w0),
+    return HelmholtzProblem(k2=_k2_from_index(nidx), source=beam_source(shape, plane, w0),
                             spacing=(H_WAVE,) * len(shape), index=nidx)
 
 

@@ -108,6 +108,18 @@ def canonical_helmholtz(k2, source, spacing, bias: str = "complex", given=None, 
     return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
 
 
+def helmholtz_symbol(shape, spacing, bias, c) -> L.usp_symbol:
+    """Symbol l(p) = (kbar^2 - |p|^2)/c of the Helmholtz canonical form for a given
+    bias kbar^2 and scale c (usp_canonical_helmholtz with both given)."""
+    grid = make_symbol(shape, spacing)
+    out = L.usp_symbol()
+    cc, b = np.zeros(2), np.zeros(2)
+    g = np.array(_c2(bias) + _c2(c))
+    L.check(L.lib().usp_canonical_helmholtz(None, 0, L.USP_BIAS_COMPLEX, _dp(g), 0.95, ct.byref(grid), ct.byref(out),
+                                            _dp(cc), _dp(b)))
+    return out
+
+
 def canonical_diffusion(mu_a, D, omega_over_v, source, spacing, vnorm: float = 0.95, dtype=torch.complex64,
                         device="cuda") -> Canonical:
     """Constant-D diffusion canonical form (usp_canonical_diffusion + usp_canonical_fields)."""

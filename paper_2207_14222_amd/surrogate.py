@@ -11,6 +11,8 @@ level (192->64, 96->32, 48->16), and a 1x1x1 head to (Re, Im).  Every
 arithmetic step runs in the library's kernels (usp_nn_*: bf16 matrix-core
 convolutions with fp32 accumulation, fp32 Adam master weights); this module
 only orders the calls and owns the device buffers (torch tensors).
+Activations are bf16 in 16-channel planes ([C/16][V][16], see usp.h), so a
+torch tensor of shape (V, C) here is only a buffer of V*C elements.
 """
 from __future__ import annotations
 
@@ -32,7 +34,7 @@ LAYERS = [
     ("d3", 192, 64, 27), ("d2", 96, 32, 27), ("d1", 48, 16, 27),
     ("head", 16, 16, 1),
 ]
-IN_CH = 3          # real input channels (the rest of the 16 are zero)
+IN_CH = 5          # real input channels (the rest of the 16 are zero)
 OUT_CH = 2         # Re, Im
 
 
@@ -64,7 +66,8 @@ class Layer:
         self.w = w.to(dev).contiguous()                     # fp32 master
         self.b = torch.zeros(cout, device=dev)
         self.wb = torch.empty(cout, taps, cin, dtype=torch.bfloat16, device=dev)
-        self.wt = torch.empty(cin, taps, cout, dtype=torch.bfloat16, device=dev)
+        self.wp = torch.empty(cout * taps * cin, dtype=torch.bfloat16, device=dev)   # forward fragments
+        self.wt = torch.empty(cout * taps * cin, dtype=torch.bfloat16, device=dev)   # input-gradient fragments
         self.gw = torch.zeros_like(self.w)
         self.gb = torch.zeros_like(self.b)
         self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
@@ -75,7 +78,12 @@ class Layer:
         lib = L.lib()
         dev = self.w.device
         L.check(lib.usp_nn_to_bf16(_p(self.w), _p(self.wb), self.w.numel(), _s(dev)))
-        L.check(lib.usp_nn_transpose_weights(_p(self.wb), _p(self.wt), self.cout, self.taps, self.cin, _s(dev)))
+        self.pack()
+
+    def pack(self):
+        lib, s = L.lib(), _s(self.w.device)
+        L.check(lib.usp_nn_pack_weights(_p(self.wb), _p(self.wp), self.cout, self.taps, self.cin, 0, s))
+        L.check(lib.usp_nn_pack_weights(_p(self.wb), _p(self.wt), self.cout, self.taps, self.cin, 1, s))
 
 
 @dataclass
@@ -161,7 +169,7 @@ class UNet3D:
     def _conv(self, name, x, out, relu=True, out_f32=False, cstore=None):
         ly = self.layers[name]
         d, h, w = self.levels[self._level(name)]
-        L.check(L.lib().usp_nn_conv3d(_p(x), _p(ly.wb), _p(ly.b), _p(out), int(out_f32), cstore or ly.cout, d, h, w,
+        L.check(L.lib().usp_nn_conv3d(_p(x), _p(ly.wp), _p(ly.b), _p(out), int(out_f32), cstore or ly.cout, d, h, w,
                                       ly.cin, ly.cout, ly.taps, 1, int(relu), _s(self.dev)))
 
     def _conv_back(self, name, g, out):
@@ -193,11 +201,12 @@ class UNet3D:
         L.check(L.lib().usp_nn_relu_backward(_p(y), _p(g), _p(out), y.numel(), int(acc), _s(self.dev)))
 
     # -- network ------------------------------------------------------------------
-    def features(self, nidx64, plane=20, n_bg=1.33, n_span=0.17, kappa_max=0.2):
-        """Input channels from the complex refractive index (complex64 [D,H,W] device tensor)."""
+    def features(self, nidx64, plane=20, w0=16.0, k0h=2 * math.pi * 0.25, n_bg=1.33, n_span=0.17, kappa_max=0.2):
+        """Input channels from the complex refractive index (complex64 [D,H,W] device tensor) and the
+        source geometry (beam on z = plane with waist w0 voxels; k0h = wavenumber x grid step)."""
         D, H, W = self.shape
-        L.check(L.lib().usp_nn_features(_p(nidx64), _p(self.a.x0), D, H, W, n_bg, n_span, kappa_max, plane,
-                                        _s(self.dev)))
+        L.check(L.lib().usp_nn_features(_p(nidx64), _p(self.a.x0), D, H, W, n_bg, n_span, kappa_max, plane, k0h,
+                                        w0, _s(self.dev)))
 
     def forward(self):
         a = self.a
@@ -296,7 +305,7 @@ class UNet3D:
                                     eps, self.step, _s(self.dev)))
             L.check(lib.usp_nn_adam(_p(ly.b), _p(ly.gb), _p(ly.mb), _p(ly.vb), None, ly.b.numel(), lr, b1, b2, eps,
                                     self.step, _s(self.dev)))
-            L.check(lib.usp_nn_transpose_weights(_p(ly.wb), _p(ly.wt), ly.cout, ly.taps, ly.cin, _s(self.dev)))
+            ly.pack()
 
     def predict_field(self, out128):
         """x0 = scale * (Re + i Im) of the last forward pass, as complex128 [D,H,W]."""

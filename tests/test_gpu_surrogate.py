@@ -41,9 +41,22 @@ def bf(x):
 
 
 def to_cf(a, shape):
-    """GPU channels-last [V][C] -> channels-first [C, D, H, W] float64 on the CPU."""
+    """16-channel planes [C/16][V][16] (any buffer shape) -> channels-first [C, D, H, W] float64 on the CPU."""
     D, H, W = shape
-    return a.float().cpu().double().reshape(D, H, W, -1).permute(3, 0, 1, 2).contiguous()
+    t = a.float().cpu().double().reshape(-1, D, H, W, 16)
+    return t.permute(0, 4, 1, 2, 3).reshape(-1, D, H, W).contiguous()
+
+
+def from_cf(x):
+    """channels-first [C, D, H, W] -> 16-channel planes [C/16][V][16] (same dtype)."""
+    C = x.shape[0]
+    return x.reshape(C // 16, 16, -1).permute(0, 2, 1).contiguous()
+
+
+def rows_to_cf(a, shape):
+    """fp32 rows [V][C] -> channels-first [C, D, H, W] float64 on the CPU."""
+    D, H, W = shape
+    return a.cpu().double().reshape(D, H, W, -1).permute(3, 0, 1, 2).contiguous()
 
 
 def w_to_torch(w, taps):
@@ -57,36 +70,49 @@ def rel(a, b):
     return float((a - b).norm() / b.norm())
 
 
+def pack(L, w, transposed):
+    cout, taps, cin = w.shape
+    pk = torch.empty(w.numel(), dtype=torch.bfloat16, device="cuda")
+    assert L.lib().usp_nn_pack_weights(_p(w), _p(pk), cout, taps, cin, int(transposed), _st()) == 0
+    return pk
+
+
 SHAPES = [(16, 16, 27), (16, 32, 27), (64, 128, 27), (192, 64, 27), (48, 16, 27), (16, 16, 1)]
+GRIDS = [(8, 16, 16), (16, 32, 32), (64, 64, 64)]   # the last takes the 4-tile-per-wave schedule
 
 
+@pytest.mark.parametrize("grid", GRIDS[:2])
 @pytest.mark.parametrize("cin,cout,taps", SHAPES)
-def test_conv_forward_input_grad_and_weight_grad(cin, cout, taps):
+def test_conv_forward_input_grad_and_weight_grad(cin, cout, taps, grid):
     _need_gpu()
     L = _lib()
-    grid = (8, 16, 16)
     D, H, W = grid
     V = D * H * W
-    print(f"[gpu-case] conv {cin}->{cout} taps {taps}", flush=True)
+    print(f"[gpu-case] conv {cin}->{cout} taps {taps} grid {grid}", flush=True)
     g = torch.Generator().manual_seed(cin * 1000 + cout)
-    x = bf(torch.randn(V, cin, generator=g)).cuda()
+    xc = bf(torch.randn(cin, D, H, W, generator=g))
+    x = from_cf(xc).cuda()
     w = bf(torch.randn(cout, taps, cin, generator=g) / math.sqrt(cin * taps)).cuda()
     b = torch.randn(cout, generator=g).cuda()
     out = torch.empty(V, cout, dtype=torch.float32, device="cuda")
-    assert L.lib().usp_nn_conv3d(_p(x), _p(w), _p(b), _p(out), 1, cout, D, H, W, cin, cout, taps, 1, 0, _st()) == 0
-    xt = to_cf(x, grid).requires_grad_(True)
+    wp = pack(L, w, False)
+    assert L.lib().usp_nn_conv3d(_p(x), _p(wp), _p(b), _p(out), 1, cout, D, H, W, cin, cout, taps, 1, 0, _st()) == 0
+    xt = xc.double().requires_grad_(True)
     wt = w_to_torch(w, taps).requires_grad_(True)
     ref = S.conv(xt, wt, b.cpu().double(), relu=False)
-    assert rel(to_cf(out, grid), ref.detach()) < 1e-5
-    # input gradient with the transposed weights
-    gy = bf(torch.randn(V, cout, generator=g)).cuda()
-    wT = torch.empty(cin, taps, cout, dtype=torch.bfloat16, device="cuda")
-    assert L.lib().usp_nn_transpose_weights(_p(w), _p(wT), cout, taps, cin, _st()) == 0
+    assert rel(rows_to_cf(out, grid), ref.detach()) < 1e-5
+    # bf16 planes output with ReLU
+    ob = torch.empty(cout // 16, V, 16, dtype=torch.bfloat16, device="cuda")
+    assert L.lib().usp_nn_conv3d(_p(x), _p(wp), _p(b), _p(ob), 0, cout, D, H, W, cin, cout, taps, 1, 1, _st()) == 0
+    assert rel(to_cf(ob, grid), torch.relu(ref.detach())) < 1e-2
+    # input gradient with the transposed packing
+    gyc = bf(torch.randn(cout, D, H, W, generator=g))
+    gy = from_cf(gyc).cuda()
+    wT = pack(L, w, True)
     gx = torch.empty(V, cin, dtype=torch.float32, device="cuda")
     assert L.lib().usp_nn_conv3d(_p(gy), _p(wT), None, _p(gx), 1, cin, D, H, W, cout, cin, taps, -1, 0, _st()) == 0
-    gyt = to_cf(gy, grid)
-    ref_gx, ref_gw = torch.autograd.grad(ref, [xt, wt], gyt)
-    assert rel(to_cf(gx, grid), ref_gx) < 1e-5
+    ref_gx, ref_gw = torch.autograd.grad(ref, [xt, wt], gyc.double())
+    assert rel(rows_to_cf(gx, grid), ref_gx) < 1e-5
     # weight and bias gradients
     nb = ct.c_size_t()
     assert L.lib().usp_nn_wgrad_workspace(D, H, W, cin, cout, taps, ct.byref(nb)) == 0
@@ -96,39 +122,128 @@ def test_conv_forward_input_grad_and_weight_grad(cin, cout, taps):
     assert L.lib().usp_nn_conv3d_wgrad(_p(x), _p(gy), _p(dw), _p(db), _p(ws), nb.value, D, H, W, cin, cout, taps,
                                        _st()) == 0
     assert rel(w_to_torch(dw, taps), ref_gw) < 1e-4
-    assert rel(db.cpu().double(), gyt.sum(dim=(1, 2, 3))) < 1e-4
+    assert rel(db.cpu().double(), gyc.double().sum(dim=(1, 2, 3))) < 1e-4
+
+
+def conv_at(xc, w, b, z, y, x, sign):
+    """Direct float64 sum at one voxel: sum_tap w[:, tap, :] @ xc[:, (z, y, x) + sign * off(tap)] (+ b)."""
+    D, H, W = xc.shape[1:]
+    out = np.zeros(w.shape[0]) if b is None else b.copy()
+    for tap in range(27):
+        dz, dy, dx = tap // 9 - 1, (tap // 3) % 3 - 1, tap % 3 - 1
+        zz, yy, xx = z + sign * dz, y + sign * dy, x + sign * dx
+        if 0 <= zz < D and 0 <= yy < H and 0 <= xx < W:
+            out += w[:, tap, :] @ xc[:, zz, yy, xx]
+    return out
+
+
+@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (16, 48)])
+def test_conv_wide_schedule(cin, cout):
+    """64^3 grid (4 voxel tiles per wave): forward and input gradient against
+    direct float64 sums on sampled voxels (faces and corners included); the
+    16 -> 16 weight gradient in full (row chunks of a larger grid)."""
+    _need_gpu()
+    L = _lib()
+    grid = GRIDS[2]
+    D, H, W = grid
+    V = D * H * W
+    print(f"[gpu-case] conv wide {cin}->{cout} grid {grid}", flush=True)
+    g = torch.Generator().manual_seed(7 + cin + cout)
+    xc = bf(torch.randn(cin, D, H, W, generator=g))
+    x = from_cf(xc).cuda()
+    w = bf(torch.randn(cout, 27, cin, generator=g) / math.sqrt(cin * 27)).cuda()
+    b = torch.randn(cout, generator=g).cuda()
+    out = torch.empty(V, cout, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d(_p(x), _p(pack(L, w, False)), _p(b), _p(out), 1, cout, D, H, W, cin, cout, 27, 1, 0,
+                                 _st()) == 0
+    gyc = bf(torch.randn(cout, D, H, W, generator=g))
+    gy = from_cf(gyc).cuda()
+    gx = torch.empty(V, cin, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d(_p(gy), _p(pack(L, w, True)), None, _p(gx), 1, cin, D, H, W, cout, cin, 27, -1, 0,
+                                 _st()) == 0
+    xn, gyn = xc.double().numpy(), gyc.double().numpy()
+    wn = w.float().cpu().double().numpy()
+    bn = b.cpu().double().numpy()
+    outn = out.cpu().double().numpy().reshape(D, H, W, cout)
+    gxn = gx.cpu().double().numpy().reshape(D, H, W, cin)
+    rng = np.random.default_rng(0)
+    pts = [tuple(int(rng.integers(0, n)) for n in grid) for _ in range(64)]
+    pts += [(0, 0, 0), (D - 1, H - 1, W - 1), (0, H - 1, 0), (D - 1, 0, W - 1), (31, 0, 17), (5, 63, 62)]
+    for (z, y, x_) in pts:
+        r = conv_at(xn, wn, bn, z, y, x_, 1)
+        assert np.linalg.norm(outn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
+        r = conv_at(gyn, wn.transpose(2, 1, 0), None, z, y, x_, -1)
+        assert np.linalg.norm(gxn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
+    if cin == cout == 16:
+        nb = ct.c_size_t()
+        assert L.lib().usp_nn_wgrad_workspace(D, H, W, cin, cout, 27, ct.byref(nb)) == 0
+        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+        dw = torch.empty(cout, 27, cin, dtype=torch.float32, device="cuda")
+        assert L.lib().usp_nn_conv3d_wgrad(_p(x), _p(gy), _p(dw), None, _p(ws), nb.value, D, H, W, cin, cout, 27,
+                                           _st()) == 0
+        xp = np.pad(xn, ((0, 0), (1, 1), (1, 1), (1, 1)))
+        G = gyn.reshape(cout, -1)
+        ref = np.empty((cout, 27, cin))
+        for tap in range(27):
+            kz, ky, kx = tap // 9, (tap // 3) % 3, tap % 3
+            ref[:, tap, :] = G @ xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(cin, -1).T
+        assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
 def test_pool_upsample_and_copies():
     _need_gpu()
     L = _lib()
-    D, H, W, C = 8, 16, 32, 16
+    D, H, W, C = 8, 16, 32, 32
     V = D * H * W
     g = torch.Generator().manual_seed(3)
-    x = bf(torch.randn(V, C, generator=g)).cuda()
-    p = torch.empty(V // 8, C, dtype=torch.bfloat16, device="cuda")
+    xc = bf(torch.randn(C, D, H, W, generator=g))
+    x = from_cf(xc).cuda()
+    p = torch.empty(C // 16, V // 8, 16, dtype=torch.bfloat16, device="cuda")
     assert L.lib().usp_nn_pool2(_p(x), _p(p), D, H, W, C, 0, _st()) == 0
-    ref = torch.nn.functional.avg_pool3d(to_cf(x, (D, H, W))[None], 2)[0]
+    ref = torch.nn.functional.avg_pool3d(xc.double()[None], 2)[0]
     assert rel(to_cf(p, (D // 2, H // 2, W // 2)), ref) < 1e-2
-    gb = torch.empty(V, C, dtype=torch.bfloat16, device="cuda")
+    gb = torch.empty(C // 16, V, 16, dtype=torch.bfloat16, device="cuda")
     assert L.lib().usp_nn_pool2(_p(p), _p(gb), D, H, W, C, 1, _st()) == 0
     pc = to_cf(p, (D // 2, H // 2, W // 2))
     assert rel(to_cf(gb, (D, H, W)), torch.nn.functional.interpolate(pc[None], scale_factor=2)[0] / 8) < 1e-2
-    # upsample into channels 16..32 of a 48-channel tensor, and its gradient
-    cat = torch.zeros(V, 48, dtype=torch.bfloat16, device="cuda")
-    assert L.lib().usp_nn_upsample2(_p(p), _p(cat), D, H, W, C, 48, 16, 0, _st()) == 0
-    up = to_cf(cat, (D, H, W))[16:32]
-    assert rel(up, torch.nn.functional.interpolate(pc[None], scale_factor=2)[0]) < 1e-2
-    gc = torch.empty(V // 8, C, dtype=torch.bfloat16, device="cuda")
-    assert L.lib().usp_nn_upsample2(_p(cat), _p(gc), D, H, W, C, 48, 16, 1, _st()) == 0
+    # upsample into channels 16..48 of a 64-channel tensor, and its gradient
+    cat = torch.zeros(4, V, 16, dtype=torch.bfloat16, device="cuda")
+    assert L.lib().usp_nn_upsample2(_p(p), _p(cat), D, H, W, C, 64, 16, 0, _st()) == 0
+    cf = to_cf(cat, (D, H, W))
+    assert rel(cf[16:48], torch.nn.functional.interpolate(pc[None], scale_factor=2)[0]) < 1e-2
+    assert float(cf[:16].abs().max()) == 0.0 and float(cf[48:].abs().max()) == 0.0
+    gc = torch.empty(C // 16, V // 8, 16, dtype=torch.bfloat16, device="cuda")
+    assert L.lib().usp_nn_upsample2(_p(cat), _p(gc), D, H, W, C, 64, 16, 1, _st()) == 0
     assert rel(to_cf(gc, (D // 2, H // 2, W // 2)), 8 * pc) < 1e-2
+    # channel copy of whole planes: channels 16..48 of cat -> 0..32 of a 32-channel tensor
+    dst = torch.empty(2, V, 16, dtype=torch.bfloat16, device="cuda")
+    assert L.lib().usp_nn_channel_copy(_p(cat), 64, 16, _p(dst), 32, 0, 32, V, _st()) == 0
+    assert torch.equal(to_cf(dst, (D, H, W)), cf[16:48])
+    # planes must be whole
+    assert L.lib().usp_nn_channel_copy(_p(cat), 64, 8, _p(dst), 32, 0, 16, V, _st()) != 0
+
+
+def test_features_against_oracle():
+    """Input channels (incl. the beam carried through the medium) vs the float64 oracle, to bf16 rounding."""
+    _need_gpu()
+    from paper_2207_14222_amd import media, surrogate
+    print("[gpu-case] features 32x16x32", flush=True)
+    shape = (32, 16, 32)
+    prob = media.helmholtz_spheres(shape=shape, count=20, width=4, w0=5.0, plane=6, seed=11)
+    nidx = prob.index.astype(np.complex64)
+    net = surrogate.UNet3D(shape, seed=0)
+    net.features(torch.from_numpy(nidx).cuda(), plane=6, w0=5.0, k0h=0.5 * math.pi)
+    got = to_cf(net.a.x0, shape)
+    ref = S.features(nidx.astype(np.complex128), 6, 5.0, 0.5 * math.pi)
+    assert float((got[:5] - torch.from_numpy(ref)).abs().max()) < 1e-2
+    assert float(got[5:].abs().max()) == 0.0
 
 
 def _oracle_params(net):
     P = {}
     for name, ly in net.layers.items():
         w = w_to_torch(ly.wb, ly.taps)
-        ci = 3 if name == "e1a" else ly.cin
+        ci = 5 if name == "e1a" else ly.cin
         co = 2 if name == "head" else ly.cout
         P[name] = (w[:co, :ci].contiguous(), ly.b.cpu().double()[:co].contiguous())
     return P
@@ -142,20 +257,20 @@ def test_network_forward_backward_against_reference():
     net = surrogate.UNet3D(shape, seed=1, scale=0.5)
     prob = media.helmholtz_spheres(shape=shape, count=30, width=4, w0=4.0, plane=4, seed=9)
     nidx = torch.from_numpy(prob.index.astype(np.complex64)).cuda()
-    net.features(nidx, plane=4)
+    net.features(nidx, plane=4, w0=4.0)
     pred = net.forward().clone()
-    feats = to_cf(net.a.x0, shape)[:3]
+    feats = to_cf(net.a.x0, shape)[:5]
     P = _oracle_params(net)
     target = torch.from_numpy((prob.source * 0.3 + 0.1j * prob.index.real).astype(np.complex64))
     L_ref, grads, pred_ref = S.gradients(P, feats, target.to(torch.complex128), 0.5)
-    pg = pred.cpu().double().reshape(*shape, 2).permute(3, 0, 1, 2)
+    pg = rows_to_cf(pred, shape)
     assert rel(pg, pred_ref) < 5e-2
     loss = net.loss(target.cuda(), grad=True)
     assert abs(loss - L_ref) < 5e-2 * L_ref
     net.backward()
     torch.cuda.synchronize()
     for name, ly in net.layers.items():
-        ci = 3 if name == "e1a" else ly.cin
+        ci = 5 if name == "e1a" else ly.cin
         co = 2 if name == "head" else ly.cout
         gw = w_to_torch(ly.gw, ly.taps)[:co, :ci].flatten()
         gr = grads[name][0].flatten()
@@ -170,7 +285,7 @@ def test_training_reduces_loss_on_one_sample():
     shape = (32, 32, 32)
     net = surrogate.UNet3D(shape, seed=2, scale=0.5)
     prob = media.helmholtz_spheres(shape=shape, count=30, width=4, w0=4.0, plane=4, seed=10)
-    net.features(torch.from_numpy(prob.index.astype(np.complex64)).cuda(), plane=4)
+    net.features(torch.from_numpy(prob.index.astype(np.complex64)).cuda(), plane=4, w0=4.0)
     target = torch.from_numpy((0.2 * prob.index.real - 0.25 + 0.05j).astype(np.complex64)).cuda()
     losses = []
     for _ in range(60):
