@@ -15,6 +15,11 @@ computes, written from the paper:
 * ``richardson`` -- Algorithm 1 (preconditioned fixed-point iteration with the
                     forward problem eliminated, Sec. 2.1) and the FP64 form of
                     outer iterative refinement.
+* ``krylov``     -- BiCGSTAB and restarted GMRES(m) on the preconditioned
+                    operator with the forward problem eliminated (the solver
+                    comparison of Sec. 4, Table 1b).
+* ``surrogate``  -- the learned initial guess's network, loss, input channels
+                    and Adam in plain PyTorch CPU float64.
 * ``theory``     -- dense-matrix quantities of the appendix theorems
                     (Lemma 2, Theorem 2, Corollary 1, condition number and rate
                     bounds) used as invariants.
