@@ -79,7 +79,16 @@ def cpu_baseline(prob, iters_needed, n_iter=3):
         x, _ = richardson.step(op, x, cp.y, 0.8)
         log(f"oracle iteration {i + 1}/{n_iter}")
     per_it = (time.perf_counter() - t0) / n_iter
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": per_it * iters_needed, "unit": "s", "cores": 1, "kind": "oracle",
+            "cpu": model, "host_cpus": os.cpu_count(),
             "sample": f"{n_iter} FP64 oracle iterations at {'x'.join(map(str, op.shape))} "
                       f"({per_it:.2f} s/iteration, numpy/pocketfft single thread), extrapolated to "
                       f"{iters_needed} iterations; oracle canonicalisation {t_prep:.1f} s not included",
@@ -200,9 +209,13 @@ def bench_learned(args, log):
     res["forward_TFLOP/s"] = round(flops / (fwd_ms * 1e-3) / 1e12, 1)
     res["forward_frac_bf16_peak"] = round(flops / (fwd_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4)
     res["forward_flops"] = flops
-    for k, v in list(res.items()):
-        if isinstance(v, float):
-            res[k] = float(f"{v:.5g}")
+    def rnd(d):
+        for k, v in list(d.items()):
+            if isinstance(v, float):
+                d[k] = float(f"{v:.5g}")
+            elif isinstance(v, dict):
+                rnd(v)
+    rnd(res)
     log(f"learned x0: {res}")
     return res
 

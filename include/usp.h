@@ -300,6 +300,49 @@ int usp_canonical_pantograph(const double* a, const double* b, int n, double lam
                              double* B_out, int32_t* idx_out, double* g0_out, double* g1_out, double* y_out,
                              double* c_out, double* bias_out);
 
+/* ---- Krylov drivers on the preconditioned system ---------------------------
+ *
+ * The comparison of Sec. 4 (Table 1b) runs Krylov methods on the same
+ * preconditioned operator.  With the forward problem eliminated (Sec. 2.1)
+ * and step size 1 the preconditioned system is P x = b with
+ *     P v = B [v - (L + I)^-1 (B v)],     b = B (L + I)^-1 y,
+ * so Algorithm 1 is x <- x + alpha (b - P x).  P v costs one pass sequence of
+ * the iteration (the same FFT passes).  Methods:
+ *   USP_KRYLOV_BICGSTAB  BiCGSTAB (van der Vorst 1992), shadow vector r_0;
+ *                        true residual checked every check_every iterations.
+ *   USP_KRYLOV_GMRES     GMRES(restart) (Saad and Schultz 1986): Arnoldi with
+ *                        classical Gram-Schmidt applied twice, Givens
+ *                        rotations; x updated and the true residual checked at
+ *                        the end of each cycle; a cycle ends early when its
+ *                        residual estimate, scaled by the ratio of true to
+ *                        preconditioned residual at the last check, is below tol.
+ * Stopping: ||y - A x||/||y|| < tol in FP64 (as usp_solve).  The handle must be
+ * plain (not USP_FLAG_REFINE), 2-D or 3-D, without a gather; the vectors are
+ * the handle's dtype, dot products and scalars are double. */
+#define USP_KRYLOV_BICGSTAB 1
+#define USP_KRYLOV_GMRES 2
+
+/* Workspace (device, 256-B aligned, caller-owned) of usp_solve_krylov for a
+ * method (restart: GMRES cycle length in [1, 64]; ignored for BiCGSTAB):
+ * BiCGSTAB 6 vectors, GMRES restart + 3 vectors, plus partial sums.
+ * Errors: INVALID (refined handle, unknown method, restart), UNSUPPORTED_SHAPE
+ * (1-D or gather). */
+int usp_krylov_workspace_bytes(usp_op op, int method, int restart, size_t* bytes);
+
+/* Solve A x = y with a Krylov method on P x = b.  x_dev: initial guess when
+ * x_is_guess, else started from 0; the solution on return.  iters_out:
+ * operator applications counted as iterations (BiCGSTAB: iterations, each
+ * applies P twice; GMRES: Arnoldi steps).  hist_est (may be NULL): GMRES:
+ * squared residual estimate ||b - P x||^2 after each Arnoldi step; BiCGSTAB:
+ * ||r||^2 of the recurrence at each check (index = iteration - 1).  hist_true
+ * (may be NULL): (iteration, ||y - A x||/||y||) pairs per check; n_true_out:
+ * number of checks.  Returns USP_OK, USP_MAXIT, USP_STAGNATED (no 1% progress
+ * over 8 checks, or a BiCGSTAB breakdown), or a negative error.  Runs on the
+ * handle's stream; synchronous with respect to the host outputs. */
+int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void* x_dev, int x_is_guess, double tol,
+                     int maxit, int check_every, void* workspace_dev, size_t workspace_bytes, int* iters_out,
+                     double* hist_est, int hist_est_cap, double* hist_true, int hist_true_cap, int* n_true_out);
+
 /* ---- learned initial guess: 3-D convolutional network kernels ----------
  *
  * A learned x0 (a network mapping the refractive-index map to the field) is

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdio>
 #include <cstring>
 #include <random>
@@ -13,6 +14,7 @@
 #include <vector>
 
 #include "../../include/usp.h"
+#include "krylov.hpp"
 #include "op.hpp"
 #include "passes.hpp"
 #include "solve1d.hpp"
@@ -446,6 +448,291 @@ int residual_1d(usp_op op, const C* y, const C* x, double* out2) {
   return 0;
 }
 
+// ---- Krylov drivers on P x = b (P v = B [v - (L + I)^-1 B v], b = B (L + I)^-1 y)
+
+constexpr int kMaxRestart = 64;
+constexpr int kVecBlocks = 2048;
+constexpr int kMdotKE = 16;
+constexpr int kKsDoubles = 1024;
+
+struct KWork {
+  long N = 0;
+  long pitch = 0;
+  int nvec = 0, nrows = 0;
+  size_t vec_bytes = 0;
+  char* base = nullptr;
+  double* rows = nullptr;
+  double* ks = nullptr;
+  size_t total = 0;
+  template <class C> C* vec(int i) const { return (C*)(base + (size_t)i * vec_bytes); }
+};
+
+int krylov_layout(usp_op op, int method, int restart, KWork* kw) {
+  if (op->d.ndim < 2 || op->has_gather) return fail(USP_ERR_UNSUPPORTED_SHAPE, "Krylov drivers need a 2-D or 3-D grid");
+  if (op->refine) return fail(USP_ERR_INVALID, "Krylov drivers need a plain (not refined) handle");
+  if (method != USP_KRYLOV_BICGSTAB && method != USP_KRYLOV_GMRES) return fail(USP_ERR_INVALID, "unknown method");
+  if (method == USP_KRYLOV_GMRES && (restart < 1 || restart > kMaxRestart))
+    return fail(USP_ERR_INVALID, "restart must be in [1, 64]");
+  const size_t es = op->dtype == USP_C64 ? 8 : 16;
+  const long N = op->d.N;
+  const long xb = op->dtype == USP_C64 ? x_blocks<float2>(op) : x_blocks<double2>(op);
+  const long mb = (N + 256L * kMdotKE - 1) / (256L * kMdotKE);
+  kw->N = N;
+  kw->pitch = std::max<long>(std::max<long>(xb, mb), kVecBlocks);
+  kw->nvec = method == USP_KRYLOV_BICGSTAB ? 6 : restart + 3;
+  kw->nrows = method == USP_KRYLOV_BICGSTAB ? 5 : std::max(5, 2 * (restart + 1));
+  kw->vec_bytes = align_up(N * es);
+  kw->total = kw->vec_bytes * kw->nvec + align_up(sizeof(double) * kw->nrows * kw->pitch) + sizeof(double) * kKsDoubles;
+  return 0;
+}
+
+int krylov_bind(KWork* kw, void* ws, size_t ws_bytes) {
+  if (!ws || ws_bytes < kw->total)
+    return fail(USP_ERR_WORKSPACE, "Krylov workspace too small: need " + std::to_string(kw->total) + " bytes");
+  if (((uintptr_t)ws) & 255) return fail(USP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  kw->base = (char*)ws;
+  kw->rows = (double*)(kw->base + kw->vec_bytes * kw->nvec);
+  kw->ks = (double*)((char*)kw->rows + align_up(sizeof(double) * kw->nrows * kw->pitch));
+  return 0;
+}
+
+int vec_blocks(long n) { return (int)std::min<long>((n + 255) / 256, kVecBlocks); }
+
+// add rows [row0, row0 + nrows) of `ncols` partials each into out[0 .. nrows)
+int ksum(usp_op op, const KWork& kw, int row0, int nrows, int ncols, double* out) {
+  hipLaunchKernelGGL(k_sum_rows, dim3(nrows), dim3(256), 0, op->st, kw.rows + (long)row0 * kw.pitch, kw.pitch, ncols,
+                     out, 0, 1 << 30);
+  LAUNCHCHK("k_sum_rows");
+  return 0;
+}
+
+// w = P v (rhs = false) or w = b from v = y (rhs = true), with fused dot partials
+template <class C>
+int kapply(usp_op op, const C* v, C* w, bool rhs, const C* q, int dots, const KWork& kw) {
+  const Dims& D = op->d;
+  const int nlines = D.n0 * D.n1;
+  C* t = (C*)op->t;
+  const C* B = (const C*)op->B;
+  int rc;
+  bool ok = with_n(D.n2, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int TPB = x_threads<C>();
+    constexpr int LPB = TPB / (N / PassPlan<N>::E);
+    const int blocks = (nlines + LPB - 1) / LPB;
+    hipLaunchKernelGGL((k_kfirst<C, N>), dim3(blocks), dim3(TPB), 0, op->st, t, v, rhs ? nullptr : B, tw_for<C>(op, N),
+                       nlines);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
+  LAUNCHCHK("k_kfirst");
+  const SymArgs sa = sym_args(op, true);
+  const int wm = sizeof(C) == 8 ? op->plan.w_mid : 0, wsy = sizeof(C) == 8 ? op->plan.w_sym : 0;
+  if (D.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa, wm))) return rc;
+  if ((rc = launch_s<C, S_SYM>(op, t, 0, sa, wsy))) return rc;
+  if (D.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa, wm))) return rc;
+  with_n(D.n2, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int TPB = x_threads<C>();
+    constexpr int LPB = TPB / (N / PassPlan<N>::E);
+    const int blocks = (nlines + LPB - 1) / LPB;
+    if (rhs)
+      hipLaunchKernelGGL((k_klast<C, N, true>), dim3(blocks), dim3(TPB), 0, op->st, t, (const C*)nullptr, B, w, q,
+                         tw_for<C>(op, N), nlines, kw.rows, kw.pitch, dots);
+    else
+      hipLaunchKernelGGL((k_klast<C, N, false>), dim3(blocks), dim3(TPB), 0, op->st, t, v, B, w, q, tw_for<C>(op, N),
+                         nlines, kw.rows, kw.pitch, dots);
+  });
+  LAUNCHCHK("k_klast");
+  return 0;
+}
+
+// true residual ||y - A x||^2 / ||y||^2 (FP64 passes) -> host
+template <class C>
+int krylov_check(usp_op op, const C* y, C* x, double* rho) {
+  int rc;
+  if ((rc = residual_passes<C>(op, x, y, (const C*)op->B, nullptr, nullptr))) return rc;
+  double host[2];
+  HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+  HIPCHK(hipStreamSynchronize(op->st));
+  *rho = std::sqrt(host[0] / host[1]);
+  return 0;
+}
+
+template <class C>
+int solve_bicgstab(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit, int check_every,
+                   const KWork& kw, int* iters_out, Monitor& mon) {
+  const long n = op->d.N;
+  C *r = kw.vec<C>(0), *rh = kw.vec<C>(1), *p = kw.vec<C>(2), *v = kw.vec<C>(3), *s = kw.vec<C>(4),
+    *t2 = kw.vec<C>(5);
+  double* ks = kw.ks;
+  const int vb = vec_blocks(n);
+  const int xb = x_blocks<C>(op);
+  int rc;
+  if ((rc = norm2(op, y, op->scal + 1))) return rc;
+  HIPCHK(hipMemsetAsync(ks, 0, sizeof(double) * kKsDoubles, op->st));
+  if ((rc = kapply<C>(op, y, s, true, nullptr, 0, kw))) return rc;   // s = b
+  if (x_is_guess) {
+    if ((rc = kapply<C>(op, x, t2, false, nullptr, 0, kw))) return rc;
+  } else {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * n, op->st));
+    HIPCHK(hipMemsetAsync(t2, 0, sizeof(C) * n, op->st));
+  }
+  hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, r, s, t2, n, kw.rows);   // r = b - P x
+  LAUNCHCHK("k_ksub");
+  if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_RHON))) return rc;   // <r^, r> = |r|^2 with r^ = r
+  HIPCHK(hipMemcpyAsync(rh, r, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+  HIPCHK(hipMemsetAsync(p, 0, sizeof(C) * n, op->st));
+  HIPCHK(hipMemsetAsync(v, 0, sizeof(C) * n, op->st));
+  hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_INIT);
+  int it = 0, status = USP_MAXIT;
+  while (it < maxit) {
+    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_BETA);
+    hipLaunchKernelGGL(k_bicg_p<C>, dim3(vb), dim3(256), 0, op->st, p, r, v, ks, n);
+    if ((rc = kapply<C>(op, p, v, false, rh, 1, kw))) return rc;          // v = P p, <r^, v>
+    if ((rc = ksum(op, kw, 0, 2, xb, ks + KS_RV))) return rc;
+    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_ALPHA);
+    hipLaunchKernelGGL(k_bicg_s<C>, dim3(vb), dim3(256), 0, op->st, s, r, v, x, p, ks, n);
+    if ((rc = kapply<C>(op, s, t2, false, nullptr, 6, kw))) return rc;    // t = P s, <t, s>, |t|^2
+    if ((rc = ksum(op, kw, 2, 3, xb, ks + KS_TS))) return rc;
+    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_OMEGA);
+    hipLaunchKernelGGL(k_bicg_r<C>, dim3(vb), dim3(256), 0, op->st, x, s, t2, r, rh, ks, n, kw.rows, kw.pitch);
+    if ((rc = ksum(op, kw, 0, 2, vb, ks + KS_RHON))) return rc;
+    if ((rc = ksum(op, kw, 2, 1, vb, ks + KS_RR))) return rc;
+    LAUNCHCHK("bicgstab iteration");
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      double rho, hk[2];
+      if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
+      HIPCHK(hipMemcpyAsync(hk, ks + KS_RR, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipStreamSynchronize(op->st));
+      mon.delta(it - 1, hk[0]);
+      const bool stag = mon.check(it, rho);
+      if (mon.nan) { status = USP_ERR_NAN; break; }
+      if (rho < tol) { status = USP_OK; break; }
+      if (hk[1] > 0.0 || stag) { status = USP_STAGNATED; break; }   // breakdown or no progress
+    }
+  }
+  if (iters_out) *iters_out = it;
+  if (status < 0) return fail(status, "non-finite values in the iteration");
+  return status;
+}
+
+template <class C>
+int solve_gmres(usp_op op, const C* y, C* x, int x_is_guess, int m, double tol, int maxit, const KWork& kw,
+                int* iters_out, Monitor& mon) {
+  const long n = op->d.N;
+  C* V = kw.vec<C>(0);   // m + 1 basis vectors, then w, then b
+  C* w = kw.vec<C>(m + 1);
+  C* b = kw.vec<C>(m + 2);
+  double* ks = kw.ks;
+  double* h1 = ks + KS_H;
+  double* h2 = h1 + 2 * (m + 1);
+  double* zc = h2 + 2 * (m + 1);
+  const int vb = vec_blocks(n);
+  const int mb = (int)((n + 256L * kMdotKE - 1) / (256L * kMdotKE));
+  auto basis = [&](int i) { return (C*)((char*)V + (size_t)i * kw.vec_bytes); };
+  const long stride = (long)(kw.vec_bytes / sizeof(C));   // elements between basis vectors
+  int rc;
+  if ((rc = norm2(op, y, op->scal + 1))) return rc;
+  if ((rc = kapply<C>(op, y, b, true, nullptr, 0, kw))) return rc;
+  if ((rc = norm2(op, b, ks + KS_NRM))) return rc;
+  double bn2 = 0.0;
+  HIPCHK(hipMemcpyAsync(&bn2, ks + KS_NRM, sizeof(double), hipMemcpyDeviceToHost, op->st));
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * n, op->st));
+  HIPCHK(hipStreamSynchronize(op->st));
+  const double bn = std::sqrt(bn2);
+  typedef std::complex<double> zd;
+  std::vector<zd> H((m + 1) * m), cs(m), sn(m), g(m + 1), z(m);
+  std::vector<double> hh(4 * (m + 1) + 1);
+  double ratio = 1.0, last_rho = -1.0;
+  int total = 0, status = USP_MAXIT;
+  if (!(bn > 0.0)) {
+    if (iters_out) *iters_out = 0;
+    return fail(USP_ERR_INVALID, "the preconditioned right-hand side is zero");
+  }
+  while (total < maxit) {
+    if ((rc = kapply<C>(op, x, w, false, nullptr, 0, kw))) return rc;
+    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, basis(0), b, w, n, kw.rows);   // r = b - P x
+    LAUNCHCHK("k_ksub");
+    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_NRM))) return rc;
+    double beta2 = 0.0;
+    HIPCHK(hipMemcpyAsync(&beta2, ks + KS_NRM, sizeof(double), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+    const double beta = std::sqrt(beta2);
+    if (!(beta == beta)) { status = USP_ERR_NAN; break; }
+    if (beta == 0.0) { status = USP_OK; break; }
+    if (last_rho >= 0.0) ratio = last_rho / std::max(beta / bn, 1e-300);
+    hipLaunchKernelGGL(k_kscale<C>, dim3(vb), dim3(256), 0, op->st, basis(0), basis(0), n, ks + KS_NRM);
+    std::fill(H.begin(), H.end(), zd(0.0));
+    std::fill(g.begin(), g.end(), zd(0.0));
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      if ((rc = kapply<C>(op, basis(j), w, false, nullptr, 0, kw))) return rc;
+      // classical Gram-Schmidt, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hc = pass == 0 ? h1 : h2;
+        hipLaunchKernelGGL((k_mdot<C, kMdotKE>), dim3(mb), dim3(256), 0, op->st, (const C*)V, stride, n, j + 1,
+                           (const C*)w, kw.rows, kw.pitch);
+        if ((rc = ksum(op, kw, 0, 2 * (j + 1), mb, hc))) return rc;
+        hipLaunchKernelGGL(k_maxpy<C>, dim3(vb), dim3(256), 0, op->st, w, (const C*)V, stride, n, j + 1,
+                           (const double*)hc, -1.0, pass == 1 ? kw.rows : nullptr);
+      }
+      LAUNCHCHK("gmres orthogonalisation");
+      if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_NRM))) return rc;
+      HIPCHK(hipMemcpyAsync(hh.data(), h1, sizeof(double) * 4 * (m + 1), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipMemcpyAsync(hh.data() + 4 * (m + 1), ks + KS_NRM, sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipStreamSynchronize(op->st));
+      for (int i = 0; i <= j; ++i)
+        H[i * m + j] = zd(hh[2 * i] + hh[2 * (m + 1) + 2 * i], hh[2 * i + 1] + hh[2 * (m + 1) + 2 * i + 1]);
+      const double hn = std::sqrt(hh[4 * (m + 1)]);
+      if (!(hn == hn)) { status = USP_ERR_NAN; break; }
+      H[(j + 1) * m + j] = hn;
+      if (hn > 0.0) hipLaunchKernelGGL(k_kscale<C>, dim3(vb), dim3(256), 0, op->st, basis(j + 1), w, n, ks + KS_NRM);
+      for (int i = 0; i < j; ++i) {
+        const zd a = H[i * m + j], c = H[(i + 1) * m + j];
+        H[i * m + j] = std::conj(cs[i]) * a + std::conj(sn[i]) * c;
+        H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+      }
+      const double den = std::sqrt(std::norm(H[j * m + j]) + std::norm(H[(j + 1) * m + j]));
+      cs[j] = H[j * m + j] / den;
+      sn[j] = H[(j + 1) * m + j] / den;
+      H[j * m + j] = den;
+      H[(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = std::conj(cs[j]) * g[j];
+      k = j + 1;
+      mon.delta(total, std::norm(g[j + 1]));
+      ++total;
+      if (hn == 0.0 || total >= maxit || std::abs(g[j + 1]) / bn * ratio < tol) break;
+    }
+    if (status == USP_ERR_NAN) break;
+    for (int i = k - 1; i >= 0; --i) {
+      zd acc = g[i];
+      for (int l = i + 1; l < k; ++l) acc -= H[i * m + l] * z[l];
+      z[i] = acc / H[i * m + i];
+    }
+    for (int i = 0; i < k; ++i) {
+      hh[2 * i] = z[i].real();
+      hh[2 * i + 1] = z[i].imag();
+    }
+    HIPCHK(hipMemcpyAsync(zc, hh.data(), sizeof(double) * 2 * k, hipMemcpyHostToDevice, op->st));
+    hipLaunchKernelGGL(k_maxpy<C>, dim3(vb), dim3(256), 0, op->st, x, (const C*)V, stride, n, k, (const double*)zc,
+                       1.0, (double*)nullptr);
+    LAUNCHCHK("k_maxpy");
+    double rho;
+    if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
+    last_rho = rho;
+    const bool stag = mon.check(total, rho);
+    if (mon.nan) { status = USP_ERR_NAN; break; }
+    if (rho < tol) { status = USP_OK; break; }
+    if (stag) { status = USP_STAGNATED; break; }
+  }
+  HIPCHK(hipStreamSynchronize(op->st));
+  if (iters_out) *iters_out = total;
+  if (status < 0) return fail(status, "non-finite values in the iteration");
+  return status;
+}
+
 void cmulh(const double a[2], const double b[2], double out[2]) {
   const double r = a[0] * b[0] - a[1] * b[1], i = a[0] * b[1] + a[1] * b[0];
   out[0] = r;
@@ -594,6 +881,42 @@ int usp_solve(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double 
   } else {
     rc = solve_plain<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, alpha, tol, maxit,
                               check_every, iters_out, mon, true);
+  }
+  if (n_true_out) *n_true_out = mon.n_true;
+  return rc;
+}
+
+int usp_krylov_workspace_bytes(usp_op op, int method, int restart, size_t* bytes) {
+  if (!op || !bytes) return fail(USP_ERR_INVALID, "NULL argument");
+  KWork kw;
+  int rc = krylov_layout(op, method, restart, &kw);
+  if (rc) return rc;
+  *bytes = kw.total;
+  return 0;
+}
+
+int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void* x_dev, int x_is_guess, double tol,
+                     int maxit, int check_every, void* ws_dev, size_t ws_bytes, int* iters_out, double* hist_est,
+                     int hist_est_cap, double* hist_true, int hist_true_cap, int* n_true_out) {
+  if (!op || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  if (maxit < 0 || check_every < 1) return fail(USP_ERR_INVALID, "maxit >= 0, check_every >= 1");
+  KWork kw;
+  int rc = krylov_layout(op, method, restart, &kw);
+  if (rc) return rc;
+  if ((rc = krylov_bind(&kw, ws_dev, ws_bytes))) return rc;
+  Monitor mon{hist_est, hist_est_cap, hist_true, hist_true_cap};
+  if (method == USP_KRYLOV_BICGSTAB) {
+    rc = op->dtype == USP_C64
+             ? solve_bicgstab<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, tol, maxit, check_every,
+                                      kw, iters_out, mon)
+             : solve_bicgstab<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, tol, maxit,
+                                       check_every, kw, iters_out, mon);
+  } else {
+    rc = op->dtype == USP_C64
+             ? solve_gmres<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, restart, tol, maxit, kw,
+                                   iters_out, mon)
+             : solve_gmres<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, restart, tol, maxit, kw,
+                                    iters_out, mon);
   }
   if (n_true_out) *n_true_out = mon.n_true;
   return rc;

@@ -411,13 +411,17 @@ __global__ void k_add_bf(uint16_t* __restrict__ dst, const uint16_t* __restrict_
 // exp(-((x - W/2)^2 + (y - H/2)^2)/w0^2) carried along z with the phase and
 // attenuation of the medium, exp(i k0h sum (n + i kappa)) (trapezoid between
 // neighbouring planes, from the source plane up and down), channels 5..15
-// zero.  One thread per (x, y) column walks z; the path sums are in double.
-__device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane, double amp, double pr, double pi,
+// zero.  One thread per (x, y) column walks z; the path sums are in double,
+// the phase is reduced to [-pi, pi] in double before the float sine/cosine.
+__device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane, float amp, double pr, double pi,
                                             double k0h, double n_bg, double n_span, double kappa_max) {
-  const double a = amp * exp(-k0h * pi);
-  const double ph = fmod(k0h * pr, 6.283185307179586);
-  float f[8] = {(float)((q.x - n_bg) / n_span), (float)(q.y / kappa_max), on_plane ? 1.f : 0.f,
-                (float)(a * cos(ph)), (float)(a * sin(ph)), 0.f, 0.f, 0.f};
+  const float a = amp * expf((float)(-k0h * pi));
+  const double t = k0h * pr;
+  const float ph = (float)(t - 6.283185307179586 * rint(t * 0.15915494309189535));
+  float sn, cs;
+  sincosf(ph, &sn, &cs);
+  float f[8] = {(float)((q.x - n_bg) / n_span), (float)(q.y / kappa_max), on_plane ? 1.f : 0.f, a * cs, a * sn,
+                0.f, 0.f, 0.f};
   uint4* w = reinterpret_cast<uint4*>(o);
   w[0] = pack8(f);
   w[1] = uint4{0u, 0u, 0u, 0u};
@@ -427,7 +431,7 @@ __global__ void k_features(const float2* __restrict__ nidx, uint16_t* __restrict
   const long cols = (long)H * W;
   for (long col = blockIdx.x * (long)blockDim.x + threadIdx.x; col < cols; col += (long)gridDim.x * blockDim.x) {
     const double dx = (double)(col % W) - 0.5 * W, dy = (double)(col / W) - 0.5 * H;
-    const double amp = exp(-(dx * dx + dy * dy) / (w0 * w0));
+    const float amp = (float)exp(-(dx * dx + dy * dy) / (w0 * w0));
     const float2 q0 = nidx[(long)plane * cols + col];
     feature_row(out + ((long)plane * cols + col) * 16, q0, true, amp, 0.0, 0.0, k0h, n_bg, n_span, kappa_max);
     double pr = 0.0, pi = 0.0;

@@ -181,9 +181,14 @@ def evaluate(net: UNet3D, wl: Workload, seeds, plain=True, log=None):
 
 
 def summarize(rows):
-    """Means over the evaluated media (times in ms)."""
+    """Means over the evaluated media (times in ms), with median and 90th percentile of
+    the iteration counts and times."""
     def m(k):
         return float(np.mean([r[k] for r in rows])) if rows and k in rows[0] else None
+
+    def q(k, scale=1.0):
+        v = np.array([r[k] for r in rows], dtype=float) * scale
+        return {"median": float(np.median(v)), "p90": float(np.percentile(v, 90))}
 
     out = {"media": len(rows), "iters_zero": m("iters_zero"), "iters_learned": m("iters_learned"),
            "t_zero_ms": 1e3 * m("t_zero"), "t_learned_ms": 1e3 * m("t_learned"), "t_infer_ms": 1e3 * m("t_infer"),
@@ -193,6 +198,9 @@ def summarize(rows):
     if rows and "t_plain" in rows[0]:
         out["t_plain_ms"] = 1e3 * m("t_plain")
         out["iters_plain"] = m("iters_plain")
+    if rows:
+        out["quantiles"] = {k: q(k, 1e3 if k.startswith("t_") else 1.0)
+                            for k in ("iters_zero", "iters_learned", "t_zero", "t_learned", "t_plain") if k in rows[0]}
     return out
 
 

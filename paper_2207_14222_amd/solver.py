@@ -281,6 +281,30 @@ class Operator:
                                      int(reps), ct.byref(p)))
         return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream}
 
+    def krylov(self, y, x=None, method="bicgstab", restart=20, tol=1e-6, maxit=10000, check_every=20,
+               hist_cap=None) -> SolveResult:
+        """usp_solve_krylov: BiCGSTAB or GMRES(restart) on the preconditioned system
+        (workspace allocated here as a torch tensor).  hist_pre holds the method's
+        squared residual estimates (see usp.h)."""
+        y = self._field(y)
+        guess = x is not None
+        x = self._field(x) if guess else torch.empty_like(y)
+        meth = {"bicgstab": L.USP_KRYLOV_BICGSTAB, "gmres": L.USP_KRYLOV_GMRES}[method]
+        nb = ct.c_size_t()
+        L.check(L.lib().usp_krylov_workspace_bytes(self.handle, meth, int(restart), ct.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        hc = maxit if hist_cap is None else hist_cap
+        hp = np.zeros(max(hc, 1))
+        ntc = maxit + 2
+        ht = np.zeros(2 * ntc)
+        it, nt = ct.c_int(), ct.c_int()
+        rc = L.check(L.lib().usp_solve_krylov(self.handle, meth, int(restart), _ptr(y), _ptr(x), int(guess),
+                                              float(tol), int(maxit), int(check_every), _ptr(ws), nb.value,
+                                              ct.byref(it), _dp(hp), hc, _dp(ht), ntc, ct.byref(nt)))
+        m = min(nt.value, ntc)
+        return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:min(it.value, hc)].copy(),
+                           hist_true=ht[:2 * m].reshape(m, 2).copy())
+
     def residual(self, y, x):
         """(||y - A x||/||y||, ||y - A x||, ||y||) in FP64."""
         rel, rn, yn = np.zeros(1), np.zeros(1), np.zeros(1)
