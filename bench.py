@@ -15,7 +15,8 @@ accumulated in FP64 every 20 iterations.  Inputs (B, y) are resident in HBM
 before the timed region.  Reported beside it: the plain complex128 solve, the
 plain complex64 solve's attainable residual, per-pass kernel times (hipEvents
 on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
-the other workloads under "modes": diffusion (plain vs refined), 96 batched
+the other workloads under "modes": BiCGSTAB and GMRES(m) on the same
+preconditioned operator, diffusion (plain vs refined), 96 batched
 2-D problems in one graph-captured schedule, and the learned initial guess
 on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
 protocol is 2000 / 200 media).
@@ -180,6 +181,44 @@ def bench_batch(args, log):
             "per_size": per_size, "max_rho": float(max(out.rho)),
             "sequential_refined_ms": round(seq_ref * 1e3, 3), "sequential_plain_c128_ms": round(seq_plain * 1e3, 3),
             "speedup_vs_sequential_plain": round(seq_plain * 1e3 / out.elapsed_ms, 2)}
+
+
+def bench_krylov(args, can128, log):
+    """Krylov drivers on the same preconditioned operator (complex128, 256^3, tol as the
+    main solve): BiCGSTAB (true residual checked every 5), GMRES(20), GMRES(5), beside the
+    plain complex128 fixed point (alpha 0.8) -- the comparison of Table 1b."""
+    import torch
+    from paper_2207_14222_amd import solver
+    op = solver.Operator(can128.symbol, can128.B)
+    y = can128.y
+    N = y.numel()
+    out = {}
+    runs = [("bicgstab", dict(method="bicgstab", check_every=5)), ("gmres20", dict(method="gmres", restart=20)),
+            ("gmres5", dict(method="gmres", restart=5))]
+    for name, kw in runs:
+        op.krylov(y, tol=args.tol, maxit=3000, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.krylov(y, tol=args.tol, maxit=3000, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        applies = 2 * r.iterations if name == "bicgstab" else r.iterations
+        out[name] = {"time_ms": round(dt * 1e3, 2), "iterations": r.iterations, "operator_applications": applies,
+                     "status": r.status_name, "rho": float(r.hist_true[-1, 1]),
+                     "ms_per_iteration": round(dt * 1e3 / max(1, r.iterations), 4)}
+        if name == "bicgstab":
+            # 43 arrays per iteration: two applications of P (13 + 14) and three vector updates (4 + 6 + 6)
+            out[name]["GB/s_per_iter"] = round(43 * N * 16 * r.iterations / dt / 1e9, 1)
+        log(f"krylov {name}: {out[name]}")
+    op.solve(y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.solve(y, alpha=args.alpha, tol=args.tol, maxit=20000, check_every=args.refine_every)
+    torch.cuda.synchronize()
+    out["fixed_point_c128"] = {"time_ms": round((time.perf_counter() - t0) * 1e3, 2), "iterations": r.iterations,
+                               "operator_applications": r.iterations, "status": r.status_name}
+    op.close()
+    return out
 
 
 def bench_learned(args, log):
@@ -361,6 +400,11 @@ def main():
                               "min_rho": float(np.min(r64.hist_true[:, 1])),
                               "reaches_tol": bool(r64.converged)}
         del op64, r64, can64
+        torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        log("Krylov drivers (complex128)")
+        extra["krylov_c128"] = bench_krylov(args, can128, log)
         torch.cuda.empty_cache()
 
     if not args.no_extra:

@@ -135,7 +135,11 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
  *   y_dev, x_dev   right-hand side and solution (dtype of the handle; complex128
  *                  in refined mode).  x_dev is read as the initial guess when
  *                  x_is_guess != 0, otherwise the iteration starts from x = 0.
- *                  On return x_dev holds the last iterate.
+ *                  x_is_guess == 2 (2-D / 3-D): the guess is judged first --
+ *                  its FP64 residual is the first hist_true entry, and if it
+ *                  is not below ||y|| the guess is discarded and the solve
+ *                  starts from x = 0 (for learned or otherwise untrusted
+ *                  guesses).  On return x_dev holds the last iterate.
  *   alpha          step size (> 0; (0, 1] is always contractive, Corollary 1).
  *   check_every    true residual evaluated (in FP64) every check_every
  *                  iterations; in refined mode this is the refinement interval

@@ -315,7 +315,24 @@ int solve_plain(usp_op op, const C* y, C* x, int x_is_guess, double alpha, doubl
   if ((rc = norm2(op, y, op->scal + 1))) return rc;
   op->pending = op->pending_first = 0;
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * op->d.N, op->st));
-  if ((rc = first_pass<C>(op, x, y, B, x_is_guess))) return rc;
+  if (x_is_guess == 2 && check_residual) {
+    // a guess whose residual is not below ||y|| is discarded: start from x = 0
+    if ((rc = residual_passes<C>(op, x, y, B, nullptr, nullptr))) return rc;
+    double h0[2];
+    HIPCHK(hipMemcpyAsync(h0, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+    const double rho0 = std::sqrt(h0[0] / h0[1]);
+    mon.check(0, rho0);
+    if (rho0 < tol) {  // the guess already solves the system
+      if (iters_out) *iters_out = 0;
+      return USP_OK;
+    }
+    if (!(rho0 < 1.0)) {
+      HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * op->d.N, op->st));
+      x_is_guess = 0;
+    }
+  }
+  if ((rc = first_pass<C>(op, x, y, B, x_is_guess ? 1 : 0))) return rc;
   std::vector<double> buf;
   int it = 0, pulled = 0, status = USP_MAXIT;
   double host[2];
@@ -361,6 +378,7 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
   int it = 0, pulled = 0, status = USP_MAXIT;
   double host[2];
   const float2* d = nullptr;
+  bool judge_guess = x_is_guess == 2;
   while (true) {
     // r = y - A (x + d) in FP64; x <- x + d; r32 = complex64(r)
     if ((rc = finalize_hist(op))) return rc;
@@ -369,6 +387,15 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
     if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
     pulled = it;
     const double rho = std::sqrt(host[0] / host[1]);
+    if (judge_guess) {
+      // a guess whose residual is not below ||y|| is discarded: restart from x = 0
+      judge_guess = false;
+      if (!(rho < 1.0)) {
+        mon.check(it, rho);
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * op->d.N, op->st));
+        continue;
+      }
+    }
     const bool stag = mon.check(it, rho);
     if (mon.nan) { status = USP_ERR_NAN; break; }
     if (rho < tol) { status = USP_OK; break; }

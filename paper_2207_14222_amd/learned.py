@@ -10,9 +10,9 @@ media instead of one medium), so ||V|| <= 0.95 for every sample, the
 symbol is shared, and the right-hand side y = -S/c (hence the scale of the
 fields the network predicts) is the same for all of them.
 
-Timed learned solve = network inference + FP64 residual check of x0 + the
-unchanged solver from x0, falling back to x0 = 0 when ||y - A x0|| >= ||y||.
-Training time is reported separately.
+Timed learned solve = network inference + the unchanged solver from x0, whose
+first FP64 residual judges the guess: x0 is discarded for x = 0 when
+||y - A x0|| >= ||y||.  Training time is reported separately.
 """
 from __future__ import annotations
 
@@ -129,14 +129,15 @@ def _sync_time():
 
 
 def learned_solve(net: UNet3D, wl: Workload, op, y, nre, x0):
-    """Inference into x0 (complex128 buffer), FP64 residual check, then the solver
-    from x0, or from 0 when ||y - A x0|| >= ||y||.  Returns (result, rho_x0, used)."""
+    """Inference into x0 (complex128 buffer), then the solver judging the guess: its
+    first FP64 residual is that of x0, and x0 is discarded for x = 0 when
+    ||y - A x0|| >= ||y||.  Returns (result, rho_x0, used)."""
     wl.features(net, nre)
     net.forward()
     net.predict_field(x0)
-    rho0, _, _ = op.residual(y, x0)
-    use = rho0 < 1.0
-    return wl.solve(op, y, x0 if use else None), rho0, bool(use)
+    r = op.solve(y, x=x0, alpha=wl.alpha, tol=wl.tol, maxit=20000, check_every=wl.k, judge_guess=True)
+    rho0 = float(r.hist_true[0, 1])
+    return r, rho0, bool(rho0 < 1.0)
 
 
 def evaluate(net: UNet3D, wl: Workload, seeds, plain=True, log=None):

@@ -230,7 +230,10 @@ class Operator:
             raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
         return t
 
-    def solve(self, y, x=None, alpha=0.8, tol=1e-6, maxit=10000, check_every=20, hist_cap=None) -> SolveResult:
+    def solve(self, y, x=None, alpha=0.8, tol=1e-6, maxit=10000, check_every=20, hist_cap=None,
+              judge_guess=False) -> SolveResult:
+        """usp_solve; with judge_guess the guess x is kept only if its residual is below ||y||
+        (hist_true[0] is then the guess's relative residual)."""
         y = self._field(y)
         guess = x is not None
         x = self._field(x) if guess else torch.empty_like(y)
@@ -240,7 +243,8 @@ class Operator:
         ht = np.zeros(2 * ntc)
         it = ct.c_int()
         nt = ct.c_int()
-        rc = L.check(L.lib().usp_solve(self.handle, _ptr(y), _ptr(x), int(guess), float(alpha), float(tol),
+        rc = L.check(L.lib().usp_solve(self.handle, _ptr(y), _ptr(x), (2 if judge_guess else 1) if guess else 0,
+                                       float(alpha), float(tol),
                                        int(maxit), int(check_every), ct.byref(it), _dp(hp), hc, _dp(ht), ntc,
                                        ct.byref(nt)))
         n = min(it.value, hc)
