@@ -15,6 +15,8 @@ computes, written from the paper:
 * ``richardson`` -- Algorithm 1 (preconditioned fixed-point iteration with the
                     forward problem eliminated, Sec. 2.1) and the FP64 form of
                     outer iterative refinement.
+* ``antisym``    -- the antisymmetrised canonical form for systems that are
+                    not accretive (Sec. 2.2), built on a 1-D operator.
 * ``krylov``     -- BiCGSTAB and restarted GMRES(m) on the preconditioned
                     operator with the forward problem eliminated (the solver
                     comparison of Sec. 4, Table 1b).

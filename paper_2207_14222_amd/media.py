@@ -31,7 +31,7 @@ H_WAVE = 0.25               # lambda / 4
 __all__ = [
     "HelmholtzProblem", "DiffusionProblem", "PantographProblem",
     "absorbing_kappa", "helmholtz_1d", "helmholtz_spheres", "sphere_index", "beam_source", "helmholtz_disks",
-    "helmholtz_homogeneous", "diffusion_blobs", "pantograph", "batch_sizes",
+    "helmholtz_homogeneous", "diffusion_blobs", "pantograph", "pantograph_constant", "batch_sizes",
 ]
 
 
@@ -214,6 +214,18 @@ def diffusion_blobs(shape=(128, 256, 256), seed=3, D=0.03, freq_hz=1e8, n_tissue
     src[(0,) + tuple(n // 2 for n in shape[1:])] = 1.0
     return DiffusionProblem(mu_a=mua, D=D, omega_over_v=2.0 * math.pi * freq_hz / v,
                             source=src, spacing=(h,) * len(shape))
+
+
+def pantograph_constant(n=1024, lam=0.9, a_value=0.1, b_value=-5.0, h=0.01, t0=1.0):
+    """Pantograph with constant coefficients (a non-accretive case for lam = 0.9,
+    a = 0.1, b = -5); x0(t) = exp(-50 (t-1)^2) before t0."""
+    t = t0 + h * np.arange(n)
+    a = np.full(n, a_value, dtype=np.complex128)
+    b = np.full(n, b_value, dtype=np.complex128)
+    lt = lam * t
+    x0l = np.where(lt < t0, np.exp(-50.0 * (lt - 1.0) ** 2), 0.0).astype(np.complex128)
+    return PantographProblem(a=a, b=b, lam=lam, t0=t0, h=h, x0_at_lam_t=x0l,
+                             x0_t0=complex(np.exp(-50.0 * (t0 - 1.0) ** 2)))
 
 
 def pantograph(n=1024, lam=0.5, b_value=5.0, h=0.01, t0=1.0):
