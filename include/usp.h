@@ -364,9 +364,10 @@ int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void
 
 /* Repack bf16 weights w [cout][taps][cin] (the forward layer's) into the
  * fragment order usp_nn_conv3d reads: transposed 0 for the forward
- * convolution (cin -> cout), 1 for the input gradient (cout -> cin).  The
- * packed array has taps * cin * cout bf16.  cin, cout multiples of 16, taps
- * 1 or 27, else USP_ERR_INVALID. */
+ * convolution (cin -> cout), 1 for the input gradient (cout -> cin).  27
+ * taps are packed as 14 tap pairs (the 28th tap zero) for the 32-deep bf16
+ * matrix-core product: the packed array has 28 * cin * cout bf16; 1 tap:
+ * cin * cout.  cin, cout multiples of 16, taps 1 or 27, else USP_ERR_INVALID. */
 int usp_nn_pack_weights(const void* w_dev, void* packed_dev, int cout, int taps, int cin, int transposed, void* stream);
 
 /* 3x3x3 (taps 27, zero padding 1) or 1x1x1 (taps 1) convolution as an
@@ -380,6 +381,9 @@ int usp_nn_pack_weights(const void* w_dev, void* packed_dev, int cout, int taps,
  * relu: apply max(0, .); bias may be NULL.  bf16 output: all cout channels
  * as planes (cstore must equal cout); out_f32: fp32 rows [V][cstore] of the
  * first cstore channels.  V must be a multiple of 16 and at most 2^30.
+ * Schedule (results agree to rounding): grids of at least 2^18 voxels with
+ * W % 64 == 0 and H % 4 == 0 (or W % 16 == 0 and H % 16 == 0) stage each
+ * 16-channel input brick in LDS; other grids read operands from global memory.
  * Supported (cin, cout, taps): the network's layer shapes (16,16), (16,32),
  * (32,16), (32,32), (32,64), (64,32), (64,64), (64,128), (128,64), (192,64),
  * (64,192), (96,32), (32,96), (48,16), (16,48) with 27 taps and (16,16)

@@ -73,8 +73,9 @@ extern "C" {
 int usp_nn_pack_weights(const void* w, void* packed, int cout, int taps, int cin, int transposed, void* stream) {
   if (!w || !packed || !planes_ok(cin) || !planes_ok(cout) || (taps != 1 && taps != 27))
     return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_wpack, dim3(grid_for((long)cout * taps * cin)), dim3(256), 0, (hipStream_t)stream,
-                     (const uint16_t*)w, (uint16_t*)packed, cout, taps, cin, transposed ? 1 : 0);
+  const long n = (taps == 27 ? 28L : 1L) * cin * cout;
+  hipLaunchKernelGGL(k_wpack, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (const uint16_t*)w,
+                     (uint16_t*)packed, cout, taps, cin, transposed ? 1 : 0);
   LAUNCHCHK("k_wpack");
   return 0;
 }
@@ -87,34 +88,52 @@ int usp_nn_conv3d(const void* in, const void* wpk, const float* bias, void* out,
   const long V = (long)D * H * W;
   if (V % 16 || V > (1l << 30)) return fail(USP_ERR_UNSUPPORTED_SHAPE, "the voxel count must be a multiple of 16");
   if (sign < 0 && relu) return fail(USP_ERR_INVALID, "the input-gradient convolution takes no ReLU");
-  const bool wide = V >= (1l << 18);  // 4 voxel tiles per wave on the large grids
-  const int per_block = wide ? 256 : 64;
-  const int blocks = (int)((V + per_block - 1) / per_block);
   hipStream_t st = (hipStream_t)stream;
   uint16_t* ob = out_f32 ? nullptr : (uint16_t*)out;
   float* of = out_f32 ? (float*)out : nullptr;
   const uint16_t* ip = (const uint16_t*)in;
-  const uint2* wp = (const uint2*)wpk;
+  const bool big = V >= (1l << 18);
+  // schedule: LDS-staged bricks on large grids whose sides fit the brick, else operands from global memory
+  const int bxt = !big ? 0 : (W % 64 == 0 && H % 4 == 0) ? 4 : (W % 16 == 0 && H % 16 == 0) ? 1 : 0;
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
-    auto go = [&](auto MVc) {
-      constexpr int mv = decltype(MVc)::value;
-      if (sign > 0) {
-        if (relu)
-          hipLaunchKernelGGL((k_conv<ci, co, tp, 1, true, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
-                             cstore, D, H, W);
+    auto launch = [&](auto SG, auto RL) {
+      constexpr int sg = decltype(SG)::value;
+      constexpr bool rl = decltype(RL)::value;
+      if constexpr (tp == 1) {
+        const uint2* wp = (const uint2*)wpk;
+        if (big)
+          hipLaunchKernelGGL((k_conv<ci, co, 1, sg, rl, 4>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, ip,
+                             wp, bias, ob, of, cstore, D, H, W);
         else
-          hipLaunchKernelGGL((k_conv<ci, co, tp, 1, false, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
-                             cstore, D, H, W);
+          hipLaunchKernelGGL((k_conv<ci, co, 1, sg, rl, 1>), dim3((unsigned)((V + 63) / 64)), dim3(256), 0, st, ip,
+                             wp, bias, ob, of, cstore, D, H, W);
       } else {
-        hipLaunchKernelGGL((k_conv<ci, co, tp, -1, false, mv>), dim3(blocks), dim3(256), 0, st, ip, wp, bias, ob, of,
-                           cstore, D, H, W);
+        const uint4* wp = (const uint4*)wpk;
+        if (bxt == 4)
+          hipLaunchKernelGGL((k_conv_lds<ci, co, sg, rl, 4>), dim3((unsigned)(V / 256)), dim3(256), 0, st, ip, wp, bias,
+                             ob, of, cstore, D, H, W);
+        else if (bxt == 1)
+          hipLaunchKernelGGL((k_conv_lds<ci, co, sg, rl, 1>), dim3((unsigned)(V / 256)), dim3(256), 0, st, ip, wp, bias,
+                             ob, of, cstore, D, H, W);
+        else if (big)
+          hipLaunchKernelGGL((k_conv27<ci, co, sg, rl, 4>), dim3((unsigned)((V + 255) / 256)), dim3(256), 0, st, ip,
+                             wp, bias, ob, of, cstore, D, H, W);
+        else
+          hipLaunchKernelGGL((k_conv27<ci, co, sg, rl, 1>), dim3((unsigned)((V + 63) / 64)), dim3(256), 0, st, ip, wp,
+                             bias, ob, of, cstore, D, H, W);
       }
     };
-    if (wide)
-      go(std::integral_constant<int, 4>{});
-    else
-      go(std::integral_constant<int, 1>{});
+    using P1 = std::integral_constant<int, 1>;
+    using M1 = std::integral_constant<int, -1>;
+    using T = std::true_type;
+    using F = std::false_type;
+    if (sign > 0) {
+      if (relu) launch(P1{}, T{});
+      else launch(P1{}, F{});
+    } else {
+      launch(M1{}, F{});
+    }
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
   LAUNCHCHK("k_conv");
@@ -157,7 +176,7 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
     const int bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
     hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
                        (int)kBiasChunk);
-    hipLaunchKernelGGL(k_bgrad_reduce, dim3(1), dim3(256), 0, st, bpart, db, bch, cout);
+    hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, st, bpart, db, bch, cout);
   }
   LAUNCHCHK("k_wgrad");
   return 0;

@@ -54,34 +54,55 @@ __device__ __forceinline__ void tap_offsets(int tap, int taps, int& dz, int& dy,
 }
 
 // Weights in fragment order.  For a convolution with CIN input and COUT
-// output channels (KC = CIN/16, NT = COUT/16) the B operand of (tap, kc, t)
-// is 64 lanes x 4 bf16:
-//   pk[((tap * KC + kc) * NT + t) * 64 + l][e] = Wc[t*16 + l%16][tap][kc*16 + 4 (l/16) + e]
-// with Wc = w (forward, w is [COUT][TAPS][CIN]) or, for the input gradient,
-// Wc[a][tap][b] = w[b][tap][a] (w is then the forward layer's [CIN][TAPS][COUT]
-// weights seen from the other side: here cin/cout are the forward layer's).
+// output channels (KC = CIN/16 input planes, NT = COUT/16 output tiles):
+// * 1 tap: the B operand of v_mfma_f32_16x16x16 bf16 for (kc, t) is 64 lanes x 4 bf16,
+//     pk[(kc * NT + t) * 64 + l][e] = Wc[t*16 + l%16][0][kc*16 + 4 (l/16) + e];
+// * 27 taps: the B operand of v_mfma_f32_16x16x32 bf16 for (tap pair tp, kc, t) is
+//   64 lanes x 8 bf16; lanes of group g = l/16 hold tap 2 tp + g/2 (zero weights
+//   for the 28th tap) and input channels kc*16 + 8 (g%2) + e:
+//     pk[((tp * KC + kc) * NT + t) * 64 + l][e] = Wc[t*16 + l%16][2 tp + g/2][kc*16 + 8 (g%2) + e].
+// The activation operand is laid out the same way (same tap and channel per
+// lane group and element), so the product sums over (tap, channel) whatever the
+// instruction's internal order of the K slots.  Wc = w (forward, w is
+// [COUT][TAPS][CIN]) or, for the input gradient, Wc[a][tap][b] = w[b][tap][a]
+// (cin/cout are the forward layer's).  Packed sizes: cin*cout (1 tap),
+// 28*cin*cout (27 taps).
 __global__ void k_wpack(const uint16_t* __restrict__ w, uint16_t* __restrict__ pk, int cout, int taps, int cin,
                         int transposed) {
   const int ci_c = transposed ? cout : cin;   // input channels of the packed convolution
   const int co_c = transposed ? cin : cout;   // its output channels
   const int KC = ci_c / 16, NT = co_c / 16;
-  const long n = (long)taps * ci_c * co_c;
+  auto wc = [&](int a, int tap, int b) -> uint16_t {
+    return transposed ? w[((long)b * taps + tap) * cin + a] : w[((long)a * taps + tap) * cin + b];
+  };
+  if (taps == 1) {
+    const long n = (long)ci_c * co_c;
+    for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
+      const int e = (int)(j & 3), l = (int)((j >> 2) & 63);
+      const long rest = j >> 8;
+      const int t = (int)(rest % NT), kc = (int)(rest / NT);
+      pk[j] = wc(t * 16 + (l & 15), 0, kc * 16 + 4 * (l >> 4) + e);
+    }
+    return;
+  }
+  const long n = 28L * ci_c * co_c;
   for (long j = blockIdx.x * (long)blockDim.x + threadIdx.x; j < n; j += (long)gridDim.x * blockDim.x) {
-    const int e = (int)(j & 3), l = (int)((j >> 2) & 63);
-    const long rest = j >> 8;
-    const int t = (int)(rest % NT), kc = (int)((rest / NT) % KC), tap = (int)(rest / ((long)NT * KC));
-    const int a = t * 16 + (l & 15), b = kc * 16 + 4 * (l >> 4) + e;   // Wc[a][tap][b]
-    pk[j] = transposed ? w[((long)b * taps + tap) * cin + a] : w[((long)a * taps + tap) * cin + b];
+    const int e = (int)(j & 7), l = (int)((j >> 3) & 63);
+    const long rest = j >> 9;
+    const int t = (int)(rest % NT), kc = (int)((rest / NT) % KC), tp = (int)(rest / ((long)NT * KC));
+    const int g = l >> 4, tap = 2 * tp + (g >> 1);
+    pk[j] = tap < taps ? wc(t * 16 + (l & 15), tap, kc * 16 + 8 * (g & 1) + e) : (uint16_t)0;
   }
 }
 
-// Implicit-GEMM convolution.  TAPS = 27 (3x3x3, padding 1) or 1 (1x1x1).
-// SIGN = +1: forward (neighbour v + off); SIGN = -1 with transposed packing
-// gives the gradient with respect to the input.  One wave computes MV tiles
-// of 16 consecutive voxels x all COUT channels, so every weight fragment
-// feeds MV matrix-core products and every activation operand NT of them.
-// Output: bf16 planes (all COUT channels), or fp32 rows [V][cstore] of the
-// first cstore channels when out_f32; bias and ReLU applied first.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ v8bf as_v8bf(uint4 q) { return __builtin_bit_cast(v8bf, q); }
+
+// 1x1x1 convolution (the head) with v_mfma_f32_16x16x16 bf16 and the 1-tap
+// packing.  SIGN = -1 with transposed packing gives the gradient with respect
+// to the input.  One wave computes MV tiles of 16 consecutive voxels x all
+// COUT channels.  Output: bf16 planes (all COUT channels), or fp32 rows
+// [V][cstore] of the first cstore channels when out_f32; bias and ReLU first.
 template <int CIN, int COUT, int TAPS, int SIGN, bool RELU, int MV>
 __global__ void __launch_bounds__(256)
 k_conv(const uint16_t* __restrict__ in, const uint2* __restrict__ wpk, const float* __restrict__ bias,
@@ -149,6 +170,171 @@ k_conv(const uint16_t* __restrict__ in, const uint2* __restrict__ wpk, const flo
           out_bf[((long)t * V + v) * 16 + i] = f2bf(val);
         }
       }
+    }
+  }
+}
+
+// Store of one 16-voxel x 16-channel accumulator tile: lane (j, g) holds
+// channel t*16 + j of voxels v0 + 4 g + e.
+template <bool RELU>
+__device__ __forceinline__ void conv_store(const v4f& acc, int t, long v0, int lane, float bb, long V,
+                                           uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore) {
+  const int j = lane & 15, g = lane >> 4;
+  const int co = t * 16 + j;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    float val = acc[e] + bb;
+    if (RELU) val = fmaxf(val, 0.f);
+    const long v = v0 + 4 * g + e;
+    if (out_f32) {
+      if (co < cstore) out_f32[v * cstore + co] = val;
+    } else {
+      out_bf[((long)t * V + v) * 16 + j] = f2bf(val);
+    }
+  }
+}
+
+// 3x3x3 convolution with v_mfma_f32_16x16x32 bf16, two taps per product
+// (27-tap packing), operands loaded from global memory.  One wave computes MV
+// tiles of 16 consecutive voxels x all COUT channels.  For grids too small or
+// too irregular for the LDS-staged kernel.
+template <int CIN, int COUT, int SIGN, bool RELU, int MV>
+__global__ void __launch_bounds__(256)
+k_conv27(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const float* __restrict__ bias,
+         uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore, int D, int H, int W) {
+  constexpr int NT = COUT / 16, KC = CIN / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int V = D * H * W;
+  const int vw = (blockIdx.x * 4 + wave) * (16 * MV);
+  if (vw >= V) return;  // whole wave; the kernel has no block barrier
+  const int i = lane & 15, g = lane >> 4;
+  int xm[MV], ym[MV], zm[MV];
+  bool live[MV];
+#pragma unroll
+  for (int m = 0; m < MV; ++m) {
+    const int v = vw + 16 * m + i;
+    live[m] = vw + 16 * m < V;
+    xm[m] = v % W;
+    ym[m] = (v / W) % H;
+    zm[m] = v / (W * H);
+  }
+  v4f acc[MV][NT];
+#pragma unroll
+  for (int m = 0; m < MV; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int tp = 0; tp < 14; ++tp) {
+    int tap = 2 * tp + (g >> 1);
+    if (tap > 26) tap = 26;  // its weights are zero
+    int dz, dy, dx;
+    tap_offsets(tap, 27, dz, dy, dx);
+    int nb[MV];
+    bool ok[MV];
+#pragma unroll
+    for (int m = 0; m < MV; ++m) {
+      const int zz = zm[m] + SIGN * dz, yy = ym[m] + SIGN * dy, xx = xm[m] + SIGN * dx;
+      ok[m] = live[m] && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      nb[m] = (zz * H + yy) * W + xx;
+    }
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      v8bf b[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = as_v8bf(wpk[((tp * KC + kc) * NT + t) * 64 + lane]);
+#pragma unroll
+      for (int m = 0; m < MV; ++m) {
+        const uint4 q = ok[m] ? *reinterpret_cast<const uint4*>(in + ((long)kc * V + nb[m]) * 16 + 8 * (g & 1))
+                              : uint4{0u, 0u, 0u, 0u};
+        const v8bf a = as_v8bf(q);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const float bb = bias ? bias[t * 16 + (lane & 15)] : 0.f;
+#pragma unroll
+    for (int m = 0; m < MV; ++m)
+      if (live[m]) conv_store<RELU>(acc[m][t], t, vw + 16 * m, lane, bb, V, out_bf, out_f32, cstore);
+  }
+}
+
+// 3x3x3 convolution, LDS-staged: a block computes a brick of 1 x BY x BX
+// output voxels (BX = 16 BXT, BY = 16 / BXT: 16 tiles of 16 voxels, 4 per
+// wave) and, for each 16-channel input plane in turn, stages the 3 x (BY+2) x
+// (BX+2) input voxels it touches (halo zero-filled at the grid faces) in LDS,
+// from where all 27 taps read their operands (16 bytes per lane, two taps per
+// v_mfma_f32_16x16x32 bf16).  Needs W % BX == 0 and H % BY == 0.
+template <int BXT> struct ConvTile {
+  static constexpr int BX = 16 * BXT, BY = 16 / BXT, SX = BX + 2, SY = BY + 2;
+  static constexpr int PLANE_U4 = 3 * SY * SX * 2;   // two 16-byte halves per staged voxel
+};
+
+template <int CIN, int COUT, int SIGN, bool RELU, int BXT>
+__global__ void __launch_bounds__(256)
+k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const float* __restrict__ bias,
+           uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore, int D, int H, int W) {
+  using TL = ConvTile<BXT>;
+  constexpr int NT = COUT / 16, KC = CIN / 16;
+  constexpr int BX = TL::BX, BY = TL::BY, SX = TL::SX, SY = TL::SY;
+  __shared__ uint4 stg[TL::PLANE_U4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const long V = (long)D * H * W;
+  const int nxb = W / BX, nyb = H / BY;
+  const int xb = blockIdx.x % nxb, yb = (blockIdx.x / nxb) % nyb, z = blockIdx.x / (nxb * nyb);
+  const int x0 = xb * BX, y0 = yb * BY;
+  // the wave's 4 tiles: tile q = 4 wave + m at row q / BXT, x offset 16 (q % BXT)
+  int lbase[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int q = 4 * wave + m, r = q / BXT, xt = q % BXT;
+    lbase[m] = (1 * SY + r + 1) * SX + 16 * xt + i + 1;
+  }
+  v4f acc[4][NT];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[m][t] = v4f{0.f, 0.f, 0.f, 0.f};
+  const uint4* in4 = reinterpret_cast<const uint4*>(in);
+  for (int kc = 0; kc < KC; ++kc) {
+    __syncthreads();  // the previous plane's reads are done
+    for (int u = tid; u < TL::PLANE_U4; u += 256) {
+      const int half = u & 1, vox = u >> 1;
+      const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
+      const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
+      uint4 q = uint4{0u, 0u, 0u, 0u};
+      if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        q = in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
+      stg[u] = q;
+    }
+    __syncthreads();
+    for (int tp = 0; tp < 14; ++tp) {
+      int tap = 2 * tp + (g >> 1);
+      if (tap > 26) tap = 26;  // its weights are zero
+      int dz, dy, dx;
+      tap_offsets(tap, 27, dz, dy, dx);
+      const int off = SIGN * ((dz * SY + dy) * SX + dx);
+      v8bf b[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) b[t] = as_v8bf(wpk[((tp * KC + kc) * NT + t) * 64 + lane]);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const v8bf a = as_v8bf(stg[(lbase[m] + off) * 2 + (g & 1)]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[m][t], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const float bb = bias ? bias[t * 16 + (lane & 15)] : 0.f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int q = 4 * wave + m, r = q / BXT, xt = q % BXT;
+      const long v0 = ((long)z * H + y0 + r) * W + x0 + 16 * xt;
+      conv_store<RELU>(acc[m][t], t, v0, lane, bb, V, out_bf, out_f32, cstore);
     }
   }
 }
@@ -256,34 +442,6 @@ k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int nchun
   }
 }
 
-// Bias gradient partials: part[b][p*16 + c] = sum over the chunk's voxels of
-// g(v, p*16 + c); grid (chunks, planes), 256 threads = 16 voxel lanes x 16
-// channels, lane sums combined in order.
-__global__ void __launch_bounds__(256)
-k_bgrad(const uint16_t* __restrict__ g, float* __restrict__ part, long V, int C, int chunk) {
-  __shared__ float sh[16][17];
-  const int c = threadIdx.x & 15, vl = threadIdx.x >> 4, p = blockIdx.y;
-  const long v0 = (long)blockIdx.x * chunk;
-  const long v1 = v0 + chunk < V ? v0 + chunk : V;
-  float s = 0.f;
-  for (long v = v0 + vl; v < v1; v += 16) s += bf2f(g[((long)p * V + v) * 16 + c]);
-  sh[vl][c] = s;
-  __syncthreads();
-  if (vl == 0) {
-    float t = 0.f;
-    for (int q = 0; q < 16; ++q) t += sh[q][c];
-    part[(long)blockIdx.x * C + p * 16 + c] = t;
-  }
-}
-__global__ void k_bgrad_reduce(const float* __restrict__ part, float* __restrict__ db, int nchunks, int C) {
-  for (int co = threadIdx.x; co < C; co += blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunks; ++c) s += part[(long)c * C + co];
-    db[co] = s;
-  }
-}
-
-// ---- pooling, upsampling, copies: 8 channels (16 bytes) per thread ----------
 __device__ __forceinline__ void unpack8(uint4 q, float* f) {
   const uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
@@ -299,6 +457,48 @@ __device__ __forceinline__ uint4 pack8(const float* f) {
   return uint4{w[0], w[1], w[2], w[3]};
 }
 
+// Bias gradient partials: part[b][p*16 + c] = sum over the chunk's voxels of
+// g(v, p*16 + c); grid (chunks, planes), 256 threads = 128 voxel lanes x 2
+// halves of 8 channels (16-byte loads); lane sums combined in order.
+__global__ void __launch_bounds__(256)
+k_bgrad(const uint16_t* __restrict__ g, float* __restrict__ part, long V, int C, int chunk) {
+  __shared__ float sh[128][17];
+  const int half = threadIdx.x & 1, vl = threadIdx.x >> 1, p = blockIdx.y;
+  const long v0 = (long)blockIdx.x * chunk;
+  const long v1 = v0 + chunk < V ? v0 + chunk : V;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (long v = v0 + vl; v < v1; v += 128) {
+    float f[8];
+    unpack8(*reinterpret_cast<const uint4*>(g + ((long)p * V + v) * 16 + 8 * half), f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[k] += f[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) sh[vl][8 * half + k] = s[k];
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    float t = 0.f;
+    for (int q = 0; q < 128; ++q) t += sh[q][threadIdx.x];
+    part[(long)blockIdx.x * C + p * 16 + threadIdx.x] = t;
+  }
+}
+// db[co] = sum over chunks (one block per channel, lanes strided over chunks, then in order)
+__global__ void __launch_bounds__(256)
+k_bgrad_reduce(const float* __restrict__ part, float* __restrict__ db, int nchunks, int C) {
+  __shared__ float sh[256];
+  const int co = blockIdx.x;
+  float s = 0.f;
+  for (int c = threadIdx.x; c < nchunks; c += 256) s += part[(long)c * C + co];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float t = 0.f;
+    for (int q = 0; q < 256; ++q) t += sh[q];
+    db[co] = t;
+  }
+}
+
+// ---- pooling, upsampling, copies: 8 channels (16 bytes) per thread ----------
 // 2x2x2 average pooling (fine D x H x W -> coarse), per plane.
 __global__ void k_pool2(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, int D, int H, int W, int C) {
   const int Do = D / 2, Ho = H / 2, Wo = W / 2;
@@ -428,29 +628,34 @@ __device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane
 }
 __global__ void k_features(const float2* __restrict__ nidx, uint16_t* __restrict__ out, int D, int H, int W,
                            double n_bg, double n_span, double kappa_max, int plane, double k0h, double w0) {
+  constexpr int ZB = 16;  // planes whose loads are issued together
   const long cols = (long)H * W;
   for (long col = blockIdx.x * (long)blockDim.x + threadIdx.x; col < cols; col += (long)gridDim.x * blockDim.x) {
     const double dx = (double)(col % W) - 0.5 * W, dy = (double)(col / W) - 0.5 * H;
     const float amp = (float)exp(-(dx * dx + dy * dy) / (w0 * w0));
     const float2 q0 = nidx[(long)plane * cols + col];
     feature_row(out + ((long)plane * cols + col) * 16, q0, true, amp, 0.0, 0.0, k0h, n_bg, n_span, kappa_max);
-    double pr = 0.0, pi = 0.0;
-    float2 prev = q0;
-    for (int z = plane + 1; z < D; ++z) {
-      const float2 q = nidx[(long)z * cols + col];
-      pr += 0.5 * ((double)prev.x + q.x);
-      pi += 0.5 * ((double)prev.y + q.y);
-      prev = q;
-      feature_row(out + ((long)z * cols + col) * 16, q, false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
-    }
-    pr = pi = 0.0;
-    prev = q0;
-    for (int z = plane - 1; z >= 0; --z) {
-      const float2 q = nidx[(long)z * cols + col];
-      pr += 0.5 * ((double)prev.x + q.x);
-      pi += 0.5 * ((double)prev.y + q.y);
-      prev = q;
-      feature_row(out + ((long)z * cols + col) * 16, q, false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
+    // towards z = D - 1, then towards z = 0, ZB planes per batch of loads
+    for (int dir = 1; dir >= -1; dir -= 2) {
+      double pr = 0.0, pi = 0.0;
+      float2 prev = q0;
+      for (int zb = plane + dir; dir > 0 ? zb < D : zb >= 0; zb += dir * ZB) {
+        float2 q[ZB];
+#pragma unroll
+        for (int e = 0; e < ZB; ++e) {
+          const int z = zb + dir * e;
+          q[e] = (z >= 0 && z < D) ? nidx[(long)z * cols + col] : float2{0.f, 0.f};
+        }
+#pragma unroll
+        for (int e = 0; e < ZB; ++e) {
+          const int z = zb + dir * e;
+          if (z < 0 || z >= D) break;
+          pr += 0.5 * ((double)prev.x + q[e].x);
+          pi += 0.5 * ((double)prev.y + q[e].y);
+          prev = q[e];
+          feature_row(out + ((long)z * cols + col) * 16, q[e], false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
+        }
+      }
     }
   }
 }

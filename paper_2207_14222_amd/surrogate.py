@@ -66,8 +66,9 @@ class Layer:
         self.w = w.to(dev).contiguous()                     # fp32 master
         self.b = torch.zeros(cout, device=dev)
         self.wb = torch.empty(cout, taps, cin, dtype=torch.bfloat16, device=dev)
-        self.wp = torch.empty(cout * taps * cin, dtype=torch.bfloat16, device=dev)   # forward fragments
-        self.wt = torch.empty(cout * taps * cin, dtype=torch.bfloat16, device=dev)   # input-gradient fragments
+        npk = (28 if taps == 27 else 1) * cout * cin
+        self.wp = torch.empty(npk, dtype=torch.bfloat16, device=dev)   # forward fragments
+        self.wt = torch.empty(npk, dtype=torch.bfloat16, device=dev)   # input-gradient fragments
         self.gw = torch.zeros_like(self.w)
         self.gb = torch.zeros_like(self.b)
         self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)

@@ -72,13 +72,13 @@ def rel(a, b):
 
 def pack(L, w, transposed):
     cout, taps, cin = w.shape
-    pk = torch.empty(w.numel(), dtype=torch.bfloat16, device="cuda")
+    pk = torch.empty((28 if taps == 27 else 1) * cout * cin, dtype=torch.bfloat16, device="cuda")
     assert L.lib().usp_nn_pack_weights(_p(w), _p(pk), cout, taps, cin, int(transposed), _st()) == 0
     return pk
 
 
 SHAPES = [(16, 16, 27), (16, 32, 27), (64, 128, 27), (192, 64, 27), (48, 16, 27), (16, 16, 1)]
-GRIDS = [(8, 16, 16), (16, 32, 32), (64, 64, 64)]   # the last takes the 4-tile-per-wave schedule
+GRIDS = [(8, 16, 16), (16, 32, 32), (64, 64, 64), (256, 32, 32)]   # the last two take the LDS-staged schedules
 
 
 @pytest.mark.parametrize("grid", GRIDS[:2])
@@ -137,14 +137,15 @@ def conv_at(xc, w, b, z, y, x, sign):
     return out
 
 
-@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (16, 48)])
-def test_conv_wide_schedule(cin, cout):
-    """64^3 grid (4 voxel tiles per wave): forward and input gradient against
-    direct float64 sums on sampled voxels (faces and corners included); the
-    16 -> 16 weight gradient in full (row chunks of a larger grid)."""
+@pytest.mark.parametrize("grid", GRIDS[2:])
+@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (16, 48), (96, 32)])
+def test_conv_wide_schedule(cin, cout, grid):
+    """Grids of 2^18 voxels (the LDS-staged schedules, 64-wide and 16-wide bricks):
+    forward and input gradient against direct float64 sums on sampled voxels
+    (faces, corners and brick edges included); the 16 -> 16 weight gradient in
+    full (row chunks of a larger grid)."""
     _need_gpu()
     L = _lib()
-    grid = GRIDS[2]
     D, H, W = grid
     V = D * H * W
     print(f"[gpu-case] conv wide {cin}->{cout} grid {grid}", flush=True)
@@ -168,7 +169,8 @@ def test_conv_wide_schedule(cin, cout):
     gxn = gx.cpu().double().numpy().reshape(D, H, W, cin)
     rng = np.random.default_rng(0)
     pts = [tuple(int(rng.integers(0, n)) for n in grid) for _ in range(64)]
-    pts += [(0, 0, 0), (D - 1, H - 1, W - 1), (0, H - 1, 0), (D - 1, 0, W - 1), (31, 0, 17), (5, 63, 62)]
+    pts += [(0, 0, 0), (D - 1, H - 1, W - 1), (0, H - 1, 0), (D - 1, 0, W - 1), (31, 0, 17), (5, H - 1, W - 2),
+            (7, 15, 15), (8, 16, 16), (3, 3, 63 % W), (2, 4, 16)]
     for (z, y, x_) in pts:
         r = conv_at(xn, wn, bn, z, y, x_, 1)
         assert np.linalg.norm(outn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
