@@ -171,7 +171,10 @@ def bench_batch(args, log):
         m = np.array(sizes) == n
         per_size[str(n)] = {"count": int(m.sum()), "median_ms": round(float(np.median(tdone[m])), 3),
                             "max_ms": round(float(tdone[m].max()), 3), "median_iterations": int(np.median(it[m]))}
+    # complex64 inner-iteration model bytes (2-D: 8 arrays per iteration); FP64 refinement passes excluded
+    inner_bytes = float(sum(8 * 8 * n * n * int(k) for n, k in zip(sizes, it)))
     return {"n_problems": len(sizes), "points": n_pts, "graph": True, "variant": variant,
+            "model_GB/s_inner": round(inner_bytes / (out.elapsed_ms * 1e-3) / 1e9, 1),
             "schedule": "persistent one-launch" if variant & 4 else "grouped launches, one captured graph per refinement cycle",
             "aggregate_time_to_tol_ms": round(out.elapsed_ms, 3), "wall_ms": round(wall * 1e3, 3),
             "all_converged": bool(all(st == 0 for st in out.status)),
@@ -231,6 +234,15 @@ def bench_learned(args, log):
     from paper_2207_14222_amd import learned, surrogate
     res, net, _ = learned.run((128, 128, 128), n_train=args.learned_train, n_test=args.learned_test,
                               epochs=args.learned_epochs, lr=2e-3, log=log)
+    # GB/s per inner iteration of the refined solver at 128^3 (12 complex64 arrays per iteration)
+    wl = learned.Workload((128, 128, 128))
+    nre = next(wl.index_maps([10000]))
+    op, y = wl.operator(nre)
+    r = wl.solve(op, y)
+    _, it_ms = op.profile(y, r.x, alpha=wl.alpha, K=50)
+    res["ms_per_iter"] = it_ms
+    res["GB/s_per_iter"] = 12 * y.numel() * 8 / (it_ms * 1e-3) / 1e9
+    op.close()
     # network forward alone: executed matrix-core flops (padded channels) per launch sequence
     flops = 0
     for name, cin, cout, taps in surrogate.LAYERS:

@@ -57,6 +57,7 @@ extern "C" {
 
 /* prepare flags */
 #define USP_FLAG_REFINE 1 /* complex64 inner iterations, FP64 outer refinement (needs USP_C128 buffers) */
+#define USP_FLAG_ANTISYM 2 /* 1-D: solve the antisymmetrised system (Sec. 2.2) on x = [x~; x~'] (2N values) */
 
 /* bias kinds for usp_smallest_circle */
 #define USP_BIAS_COMPLEX 0
@@ -332,6 +333,12 @@ int usp_canonical_pantograph(const double* a, const double* b, int n, double lam
  * Errors: INVALID (refined handle, unknown method, restart), UNSUPPORTED_SHAPE
  * (1-D or gather). */
 int usp_krylov_workspace_bytes(usp_op op, int method, int restart, size_t* bytes);
+
+/* Test hook: w = P v (rhs 0) or w = b = B (L + I)^-1 v (rhs 1), one pass
+ * sequence of the iteration (Sec. 2.1's eliminated form, step size 1).  Same
+ * handle restrictions and workspace as usp_solve_krylov with
+ * USP_KRYLOV_BICGSTAB (only its partial-sum area is used).  Synchronises. */
+int usp_apply_precond(usp_op op, const void* v_dev, void* w_dev, int rhs, void* workspace_dev, size_t workspace_bytes);
 
 /* Solve A x = y with a Krylov method on P x = b.  x_dev: initial guess when
  * x_is_guess, else started from 0; the solution on return.  iters_out:

@@ -17,6 +17,7 @@ USP_ERR_INVALID, USP_ERR_UNSUPPORTED_SHAPE, USP_ERR_NOT_CONTRACTIVE = -1, -2, -3
 USP_ERR_HIP, USP_ERR_NAN, USP_ERR_WORKSPACE = -4, -5, -6
 USP_C64, USP_C128 = 0, 1
 USP_FLAG_REFINE = 1
+USP_FLAG_ANTISYM = 2
 USP_BIAS_COMPLEX, USP_BIAS_REAL = 0, 1
 USP_KRYLOV_BICGSTAB, USP_KRYLOV_GMRES = 1, 2
 
@@ -30,7 +31,7 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_autotune_batched", "usp_nn_conv3d", "usp_nn_wgrad_workspace", "usp_nn_conv3d_wgrad",
            "usp_nn_pool2", "usp_nn_upsample2", "usp_nn_channel_copy", "usp_nn_relu_backward", "usp_nn_add",
            "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_pack_weights", "usp_nn_to_bf16",
-           "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov"]
+           "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -116,6 +117,7 @@ def lib():
     L.usp_nn_to_bf16.argtypes = [P, P, LG, P]
     L.usp_nn_pred_to_field.argtypes = [P, F, P, LG, P]
     L.usp_krylov_workspace_bytes.argtypes = [P, I, I, ct.POINTER(ct.c_size_t)]
+    L.usp_apply_precond.argtypes = [P, P, P, I, P, ct.c_size_t]
     L.usp_solve_krylov.argtypes = [P, I, I, P, P, I, D, I, I, P, ct.c_size_t, IP, DP, I, DP, I, IP]
     L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,
                                            DP, DP, DP]

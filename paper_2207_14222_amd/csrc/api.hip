@@ -428,9 +428,14 @@ int solve_1d(usp_op op, const C* y, C* x, int x_is_guess, double alpha, double t
   bool ok = with_n(n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     constexpr int T = N / LinePlan<N>::E;
-    hipLaunchKernelGGL((k_solve1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
-                       tw_for<C>(op, N), s, alpha, tol, maxit, check_every, x_is_guess, op->hist, op->hist_true,
-                       kHist, op->info);
+    if (op->antisym)
+      hipLaunchKernelGGL((k_solve1d_as<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
+                         (const int*)(gi ? op->adj_j : nullptr), (const C*)op->adj_w, tw_for<C>(op, N), s, alpha, tol,
+                         maxit, check_every, x_is_guess, op->hist, op->hist_true, kHist, op->info, (double*)nullptr);
+    else
+      hipLaunchKernelGGL((k_solve1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
+                         tw_for<C>(op, N), s, alpha, tol, maxit, check_every, x_is_guess, op->hist, op->hist_true,
+                         kHist, op->info);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "1-D length");
   LAUNCHCHK("k_solve1d");
@@ -465,8 +470,13 @@ int residual_1d(usp_op op, const C* y, const C* x, double* out2) {
   bool ok = with_n(n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     constexpr int T = N / LinePlan<N>::E;
-    hipLaunchKernelGGL((k_residual1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
-                       op->twd[ilog2(N)], s, op->scal);
+    if (op->antisym)
+      hipLaunchKernelGGL((k_solve1d_as<C, N>), dim3(1), dim3(T), 0, op->st, (C*)x, y, (const C*)op->B, gi, g0, g1,
+                         (const int*)(gi ? op->adj_j : nullptr), (const C*)op->adj_w, tw_for<C>(op, N), s, 0.0, 0.0,
+                         0, 1, 1, op->hist, op->hist_true, kHist, op->info, op->scal);
+    else
+      hipLaunchKernelGGL((k_residual1d<C, N>), dim3(1), dim3(T), 0, op->st, x, y, (const C*)op->B, gi, g0, g1,
+                         op->twd[ilog2(N)], s, op->scal);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "1-D length");
   LAUNCHCHK("k_residual1d");
@@ -826,6 +836,11 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
   op->scal = (double*)(w + lay.scal);
   op->hist_true = (double*)(w + lay.hist_true);
   op->info = (Solve1DInfo*)(w + lay.info);
+  op->antisym = (flags & USP_FLAG_ANTISYM) != 0;
+  if (op->antisym) {
+    op->adj_j = (int*)(w + lay.adj_j);
+    op->adj_w = w + lay.adj_w;
+  }
   cmulh(L->s, L->a0, op->sa0);
   cmulh(L->s, L->a1, op->sa1);
   cmulh(L->s, L->a2, op->sa2);
@@ -854,6 +869,67 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
         hipMemcpyAsync(op->twd[l], td.data(), n * sizeof(double2), hipMemcpyHostToDevice, op->st) != hipSuccess ||
         hipStreamSynchronize(op->st) != hipSuccess)
       return cleanup(fail(USP_ERR_HIP, "twiddle upload failed"));
+  }
+  if (op->antisym) {
+    // table of the adjoint gather G*: row k lists (j, conj(g)) for every G[j][k] = g
+    const long n = d.N;
+    const size_t es = dtype == USP_C64 ? 8 : 16;
+    std::vector<int> aj(n * kAdjMax, -1);
+    std::vector<char> aw(n * kAdjMax * es, 0);
+    if (gather) {
+      std::vector<int> gi(n);
+      std::vector<char> g0(n * es), g1(n * es);
+      if (hipStreamSynchronize(op->st) != hipSuccess ||
+          hipMemcpy(gi.data(), gather->idx_dev, n * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(g0.data(), gather->g0_dev, n * es, hipMemcpyDeviceToHost) != hipSuccess ||
+          hipMemcpy(g1.data(), gather->g1_dev, n * es, hipMemcpyDeviceToHost) != hipSuccess)
+        return cleanup(fail(USP_ERR_HIP, "gather readback failed"));
+      std::vector<int> cnt(n, 0);
+      bool wide = false;
+      auto add = [&](long k, long j, const char* g) {
+        bool zero;  // by value: weights of empty rows may be -0.0
+        if (es == 8) {
+          float2 v;
+          std::memcpy(&v, g, 8);
+          zero = v.x == 0.0f && v.y == 0.0f;
+        } else {
+          double2 v;
+          std::memcpy(&v, g, 16);
+          zero = v.x == 0.0 && v.y == 0.0;
+        }
+        if (zero) return;
+        if (cnt[k] >= kAdjMax) {
+          wide = true;
+          return;
+        }
+        const int a = cnt[k]++;
+        aj[k * kAdjMax + a] = (int)j;
+        char* dst = aw.data() + (k * kAdjMax + a) * es;
+        std::memcpy(dst, g, es);
+        if (es == 8) {  // conjugate
+          float im;
+          std::memcpy(&im, dst + 4, 4);
+          im = -im;
+          std::memcpy(dst + 4, &im, 4);
+        } else {
+          double im;
+          std::memcpy(&im, dst + 8, 8);
+          im = -im;
+          std::memcpy(dst + 8, &im, 8);
+        }
+      };
+      for (long j = 0; j < n; ++j) {
+        const long i0 = std::min<long>(std::max(gi[j], 0), n - 1);
+        const long i1 = std::min<long>(i0 + 1, n - 1);
+        add(i0, j, g0.data() + j * es);
+        add(i1, j, g1.data() + j * es);
+      }
+      if (wide) return cleanup(fail(USP_ERR_UNSUPPORTED_SHAPE, "the adjoint gather has more than 8 entries per row"));
+    }
+    if (hipMemcpyAsync(op->adj_j, aj.data(), aj.size() * sizeof(int), hipMemcpyHostToDevice, op->st) != hipSuccess ||
+        hipMemcpyAsync(op->adj_w, aw.data(), aw.size(), hipMemcpyHostToDevice, op->st) != hipSuccess ||
+        hipStreamSynchronize(op->st) != hipSuccess)
+      return cleanup(fail(USP_ERR_HIP, "adjoint table upload failed"));
   }
   if (op->refine) {
     hipLaunchKernelGGL(k_to_c64, dim3(1024), dim3(256), 0, op->st, (const double2*)B_dev, op->B32, d.N);
@@ -911,6 +987,19 @@ int usp_solve(usp_op op, const void* y_dev, void* x_dev, int x_is_guess, double 
   }
   if (n_true_out) *n_true_out = mon.n_true;
   return rc;
+}
+
+int usp_apply_precond(usp_op op, const void* v_dev, void* w_dev, int rhs, void* ws_dev, size_t ws_bytes) {
+  if (!op || !v_dev || !w_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  KWork kw;
+  int rc = krylov_layout(op, USP_KRYLOV_BICGSTAB, 0, &kw);
+  if (rc) return rc;
+  if ((rc = krylov_bind(&kw, ws_dev, ws_bytes))) return rc;
+  rc = op->dtype == USP_C64 ? kapply<float2>(op, (const float2*)v_dev, (float2*)w_dev, rhs != 0, nullptr, 0, kw)
+                            : kapply<double2>(op, (const double2*)v_dev, (double2*)w_dev, rhs != 0, nullptr, 0, kw);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(op->st));
+  return 0;
 }
 
 int usp_krylov_workspace_bytes(usp_op op, int method, int restart, size_t* bytes) {

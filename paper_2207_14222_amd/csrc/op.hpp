@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/usp.h"
-#include "solve1d.hpp"
+#include "antisym.hpp"
 
 namespace usp_detail {
 
@@ -59,7 +59,7 @@ bool with_n(int n, F&& f) {
 inline size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t t = 0, S = 0, B32 = 0, r32 = 0, d32 = 0;
+  size_t t = 0, S = 0, B32 = 0, r32 = 0, d32 = 0, adj_j = 0, adj_w = 0;
   size_t partials = 0, hist = 0, scal = 0, hist_true = 0, info = 0;
   size_t twf[11] = {0}, twd[11] = {0};
   size_t total = 0;
@@ -96,6 +96,9 @@ inline int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, D
   const bool refine = (flags & USP_FLAG_REFINE) != 0;
   if (refine && dtype != USP_C128) return fail(USP_ERR_INVALID, "refined mode needs USP_C128 buffers");
   if (refine && dims->ndim == 1) return fail(USP_ERR_INVALID, "refined mode is for 2-D / 3-D grids");
+  const bool antisym = (flags & USP_FLAG_ANTISYM) != 0;
+  if (antisym && (dims->ndim != 1 || refine)) return fail(USP_ERR_INVALID, "the antisymmetrised form is for 1-D handles");
+  if (flags & ~(USP_FLAG_REFINE | USP_FLAG_ANTISYM)) return fail(USP_ERR_INVALID, "unknown flag");
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -112,6 +115,10 @@ inline int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, D
       lay->r32 = take(N * 8);
       lay->d32 = take(N * 8);
     }
+  }
+  if (antisym) {  // adjoint-gather table
+    lay->adj_j = take(sizeof(int) * N * usp::kAdjMax);
+    lay->adj_w = take(16 * N * usp::kAdjMax);
   }
   // one row of per-block partials per pending iteration, plus a residual row and a norm row
   lay->nblk = (long)dims->n0 * dims->n1 + 4096;
@@ -158,6 +165,9 @@ struct usp_op_s {
   double* scal = nullptr;
   double* hist_true = nullptr;
   usp::Solve1DInfo* info = nullptr;
+  bool antisym = false;
+  int* adj_j = nullptr;   // adjoint gather table (antisymmetrised form)
+  void* adj_w = nullptr;
   float2* twf[11] = {nullptr};
   double2* twd[11] = {nullptr};
   // symbol multiplier constants

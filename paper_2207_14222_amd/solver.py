@@ -187,14 +187,17 @@ class SolveResult:
 class Operator:
     """A prepared operator handle (usp_prepare_operator) with its workspace tensor."""
 
-    def __init__(self, symbol: L.usp_symbol, B: torch.Tensor, refine: bool = False, gather=None):
+    def __init__(self, symbol: L.usp_symbol, B: torch.Tensor, refine: bool = False, gather=None,
+                 antisym: bool = False):
+        """antisym: solve the antisymmetrised system (1-D): fields are (2, N), [x~; x~']."""
         if not B.is_cuda:
             raise ValueError("B must be a device tensor")
         self.B = B
         self.device = B.device
         self.dtype = B.dtype
         self.dt = L.USP_C64 if B.dtype == torch.complex64 else L.USP_C128
-        self.flags = L.USP_FLAG_REFINE if refine else 0
+        self.flags = (L.USP_FLAG_REFINE if refine else 0) | (L.USP_FLAG_ANTISYM if antisym else 0)
+        self.field_shape = (2,) + tuple(B.shape) if antisym else tuple(B.shape)
         self.symbol = symbol
         self.gather = gather   # keep device arrays alive
         nbytes = ct.c_size_t()
@@ -212,7 +215,7 @@ class Operator:
 
     @property
     def shape(self):
-        return tuple(self.B.shape)
+        return self.field_shape
 
     def close(self):
         if getattr(self, "handle", None):
@@ -308,6 +311,16 @@ class Operator:
         m = min(nt.value, ntc)
         return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:min(it.value, hc)].copy(),
                            hist_true=ht[:2 * m].reshape(m, 2).copy())
+
+    def apply_precond(self, v, rhs=False):
+        """usp_apply_precond: P v, or b = B (L + I)^-1 v with rhs."""
+        v = self._field(v)
+        w = torch.empty_like(v)
+        nb = ct.c_size_t()
+        L.check(L.lib().usp_krylov_workspace_bytes(self.handle, L.USP_KRYLOV_BICGSTAB, 0, ct.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        L.check(L.lib().usp_apply_precond(self.handle, _ptr(v), _ptr(w), int(rhs), _ptr(ws), nb.value))
+        return w
 
     def residual(self, y, x):
         """(||y - A x||/||y||, ||y - A x||, ||y||) in FP64."""

@@ -134,3 +134,18 @@ def test_krylov_initial_guess_and_rejections():
                                   ct.c_void_p(x.data_ptr()), 0, 1e-6, 10, 1, ct.c_void_p(ws.data_ptr()),
                                   ws.numel(), ct.byref(it), None, 0, None, 0, None)
     assert rc == L.USP_ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("grid", ["2d", "3d"])
+def test_apply_precond_matches_oracle(grid):
+    _need_gpu()
+    p = _problems()[grid]
+    _announce(f"apply_precond {grid} c128")
+    cp, op_o = oracle_helmholtz(p)
+    can, op = gpu_helmholtz(p, "c128")
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(op_o.shape) + 1j * rng.standard_normal(op_o.shape)
+    w = op.apply_precond(torch.from_numpy(v).cuda())
+    assert rel(to_np(w), K.precond_apply(op_o, v)) < 1e-13
+    b = op.apply_precond(can.y, rhs=True)
+    assert rel(to_np(b), K.precond_rhs(op_o, cp.y)) < 1e-13
