@@ -16,7 +16,8 @@ before the timed region.  Reported beside it: the plain complex128 solve, the
 plain complex64 solve's attainable residual, per-pass kernel times (hipEvents
 on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
 the other workloads under "modes": BiCGSTAB and GMRES(m) on the same
-preconditioned operator, diffusion (plain vs refined), 96 batched
+preconditioned operator, the pantograph in direct and antisymmetrised
+form, diffusion (plain vs refined), 96 batched
 2-D problems in one graph-captured schedule, and the learned initial guess
 on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
 protocol is 2000 / 200 media).
@@ -224,6 +225,39 @@ def bench_krylov(args, can128, log):
     return out
 
 
+def bench_pantograph(args, log):
+    """Pantograph (N = 1024, complex128, single workgroup): the direct canonical form
+    and the antisymmetrised one on the accretive case (lam 0.5, b 5; tol 1e-9), and the
+    antisymmetrised one on the non-accretive case (lam 0.9, a 0.1, b -5), where the direct
+    form diverges; times include the whole solve in one launch."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    out = {}
+
+    def run(pp, antisym, alpha, tol, maxit, check):
+        can = solver.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0)
+        op = solver.Operator(can.symbol, can.B, gather=can.gather, antisym=antisym)
+        y = torch.stack([torch.zeros_like(can.y), can.y]).contiguous() if antisym else can.y
+        op.solve(y, alpha=alpha, tol=tol, maxit=maxit, check_every=check)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = op.solve(y, alpha=alpha, tol=tol, maxit=maxit, check_every=check)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return {"time_ms": round(dt * 1e3, 3), "iterations": r.iterations, "status": r.status_name,
+                "rho": float(r.hist_true[-1, 1]) if len(r.hist_true) else None,
+                "us_per_iteration": round(dt * 1e6 / max(1, r.iterations), 2)}
+
+    acc = media.pantograph(n=1024, b_value=5.0)
+    out["accretive_direct"] = run(acc, False, 0.9, 1e-9, 20000, 1)
+    out["accretive_antisym"] = run(acc, True, 1.0, 1e-9, 200000, 100)
+    non = media.pantograph_constant(n=1024)
+    out["nonaccretive_direct"] = run(non, False, 0.8, 1e-8, 2000, 1)
+    out["nonaccretive_antisym_20000"] = run(non, True, 1.0, 1e-8, 20000, 1000)
+    log(f"pantograph: {out}")
+    return out
+
+
 def bench_learned(args, log):
     """Learned initial guess on 128^3 random-sphere media (shared canonical scaling):
     training data from solves of the method (seeds 0..), Adam training of the
@@ -418,6 +452,10 @@ def main():
         log("Krylov drivers (complex128)")
         extra["krylov_c128"] = bench_krylov(args, can128, log)
         torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        log("pantograph: direct and antisymmetrised forms")
+        extra["pantograph"] = bench_pantograph(args, log)
 
     if not args.no_extra:
         log("diffusion workload")
