@@ -15,6 +15,9 @@ computes, written from the paper:
 * ``richardson`` -- Algorithm 1 (preconditioned fixed-point iteration with the
                     forward problem eliminated, Sec. 2.1) and the FP64 form of
                     outer iterative refinement.
+* ``flux``       -- steady diffusion in flux form with a tensor diffusion
+                    coefficient (Sec. 3.2): [u; J] system, 3 x 3 block symbol,
+                    per-voxel blocks of V, equilibration and scaling.
 * ``antisym``    -- the antisymmetrised canonical form for systems that are
                     not accretive (Sec. 2.2), built on a 1-D operator.
 * ``krylov``     -- BiCGSTAB and restarted GMRES(m) on the preconditioned

@@ -31,7 +31,7 @@ H_WAVE = 0.25               # lambda / 4
 __all__ = [
     "HelmholtzProblem", "DiffusionProblem", "PantographProblem",
     "absorbing_kappa", "helmholtz_1d", "helmholtz_spheres", "sphere_index", "beam_source", "helmholtz_disks",
-    "helmholtz_homogeneous", "diffusion_blobs", "pantograph", "pantograph_constant", "batch_sizes",
+    "helmholtz_homogeneous", "diffusion_blobs", "pantograph", "pantograph_constant", "batch_sizes", "FluxDiffusionProblem", "diffusion_ring",
 ]
 
 
@@ -189,6 +189,42 @@ def helmholtz_homogeneous(shape, nidx=1.0 + 0.02j, source="point"):
     src = np.zeros(shape, dtype=np.complex128)
     src[tuple(n // 2 for n in shape)] = 1.0
     return HelmholtzProblem(k2=_k2_from_index(idx), source=src, spacing=(H_WAVE,) * len(shape), index=idx)
+
+
+@dataclass
+class FluxDiffusionProblem:
+    """Inputs of the steady diffusion equation in flux form, div J + mu u = S,
+    D^-1 J + grad u = 0, on a 2-D grid (axis 1 = x, axis 0 = y)."""
+    mu: np.ndarray            # complex128 (n0, n1) absorption rate
+    D: np.ndarray             # complex128 (n0, n1, 2, 2) diffusion tensor [[Dxx, Dxy], [Dyx, Dyy]]
+    source: np.ndarray        # complex128 (n0, n1)
+    h: float
+
+
+def diffusion_ring(n=256, h=0.1, D_bg=2.0, D_t=25.0, D_r=1.0, radius=7.0, width=2.0, mu_bg=0.01,
+                   mu_abs=20.0, abs_rows=16, src_row=8):
+    """Anisotropic diffusion: a ring (radius and width in the units of h) where D is
+    D_t along the tangent and D_r along the radius, D_bg elsewhere; absorption mu_bg
+    with an absorbing layer ramping to mu_abs over the last abs_rows rows; a unit point
+    source on row src_row at the centre column."""
+    c = (np.arange(n) - n / 2) * h
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    r = np.hypot(xx, yy)
+    D = np.zeros((n, n, 2, 2), dtype=np.complex128)
+    D[..., 0, 0] = D_bg
+    D[..., 1, 1] = D_bg
+    ring = np.abs(r - radius) < width / 2
+    rx, ry = xx[ring] / r[ring], yy[ring] / r[ring]          # radial unit vector; tangent (-ry, rx)
+    D[ring, 0, 0] = D_t * ry * ry + D_r * rx * rx
+    D[ring, 0, 1] = -D_t * ry * rx + D_r * rx * ry
+    D[ring, 1, 0] = D[ring, 0, 1]
+    D[ring, 1, 1] = D_t * rx * rx + D_r * ry * ry
+    mu = np.full((n, n), mu_bg, dtype=np.complex128)
+    for i in range(abs_rows):
+        mu[n - abs_rows + i, :] = mu_bg + mu_abs * (i + 1) / abs_rows
+    src = np.zeros((n, n), dtype=np.complex128)
+    src[src_row, n // 2] = 1.0
+    return FluxDiffusionProblem(mu=mu, D=D, source=src, h=float(h))
 
 
 def batch_sizes(nprob=96, seed=4, choices=(128, 256, 512, 1024)):
