@@ -31,7 +31,8 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_autotune_batched", "usp_nn_conv3d", "usp_nn_wgrad_workspace", "usp_nn_conv3d_wgrad",
            "usp_nn_pool2", "usp_nn_upsample2", "usp_nn_channel_copy", "usp_nn_relu_backward", "usp_nn_add",
            "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_pack_weights", "usp_nn_to_bf16",
-           "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond"]
+           "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond",
+           "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -53,6 +54,11 @@ class usp_batch_item(ct.Structure):
 
 class usp_batch_result(ct.Structure):
     _fields_ = [("iterations", ct.c_int), ("status", ct.c_int), ("rho", ct.c_double), ("t_done_ms", ct.c_double)]
+
+
+class usp_flux_symbol(ct.Structure):
+    _fields_ = [("n0", ct.c_int), ("n1", ct.c_int), ("h", ct.c_double), ("s", ct.c_double * 3),
+                ("c", ct.c_double), ("mubar", ct.c_double * 2), ("dibar", (ct.c_double * 2) * 4)]
 
 
 class usp_gather(ct.Structure):
@@ -119,6 +125,11 @@ def lib():
     L.usp_krylov_workspace_bytes.argtypes = [P, I, I, ct.POINTER(ct.c_size_t)]
     L.usp_apply_precond.argtypes = [P, P, P, I, P, ct.c_size_t]
     L.usp_solve_krylov.argtypes = [P, I, I, P, P, I, D, I, I, P, ct.c_size_t, IP, DP, I, DP, I, IP]
+    FS = ct.POINTER(usp_flux_symbol)
+    L.usp_canonical_flux.argtypes = [DP, DP, DP, I, I, D, D, FS, DP, DP, DP]
+    L.usp_flux_workspace_bytes.argtypes = [FS, I, ct.POINTER(ct.c_size_t)]
+    L.usp_flux_solve.argtypes = [FS, I, P, P, P, P, I, D, D, I, I, P, ct.c_size_t, P, IP, DP, I, DP, I, IP]
+    L.usp_flux_residual.argtypes = [FS, I, P, P, P, P, P, ct.c_size_t, P, DP]
     L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,
                                            DP, DP, DP]
     for name in EXPORTS:

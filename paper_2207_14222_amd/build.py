@@ -26,7 +26,7 @@ HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["api.hip", "batch.hip", "nn.hip", "canon.cpp"]
+SOURCES = ["api.hip", "batch.hip", "nn.hip", "flux.hip", "canon.cpp"]
 
 
 def _compile(src: str) -> str:

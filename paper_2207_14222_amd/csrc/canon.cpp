@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstddef>
+#include <complex>
 #include <cstdint>
 #include <numeric>
 #include <random>
@@ -302,5 +303,124 @@ extern "C" int usp_canonical_pantograph(const double* a, const double* b, int n,
   }
   y_out[0] += x0_t0[0] / h / c;
   y_out[1] += x0_t0[1] / h / c;
+  return 0;
+}
+
+// Steady diffusion in flux form (Sec. 3.2, Eq. diffusion-equation-matrix-form)
+// on a 2-D grid: biases from smallest circles, symmetric equilibration of the
+// radii, c from the largest per-voxel spectral norm of S V~ S.
+namespace {
+void circle_of(const std::vector<double>& pts, double* centre, double* R, int* rc) {
+  const size_t n = pts.size() / 2;
+  bool same = true;
+  for (size_t i = 1; i < n && same; ++i) same = pts[2 * i] == pts[0] && pts[2 * i + 1] == pts[1];
+  if (same) {
+    centre[0] = pts[0];
+    centre[1] = pts[1];
+    *R = 0.0;
+    *rc = 0;
+    return;
+  }
+  *rc = usp_smallest_circle(pts.data(), n, USP_BIAS_COMPLEX, centre, R);
+}
+}  // namespace
+
+extern "C" int usp_canonical_flux(const double* mu, const double* D, const double* src, int n0, int n1, double h,
+                                  double vnorm, usp_flux_symbol* sym, double* bu_out, double* b2_out,
+                                  double* y_out) {
+  if (!mu || !D || !src || !sym || !bu_out || !b2_out || !y_out || n0 < 2 || n1 < 2 || !(h > 0.0) ||
+      !(vnorm > 0.0 && vnorm < 1.0))
+    return USP_ERR_INVALID;
+  const size_t n = (size_t)n0 * n1;
+  for (size_t i = 0; i < 2 * n; ++i)
+    if (!std::isfinite(mu[i]) || !std::isfinite(src[i])) return USP_ERR_NAN;
+  for (size_t i = 0; i < 8 * n; ++i)
+    if (!std::isfinite(D[i])) return USP_ERR_NAN;
+  using cd = std::complex<double>;
+  // D^-1 per voxel
+  std::vector<cd> Di(4 * n);
+  for (size_t v = 0; v < n; ++v) {
+    const cd a(D[8 * v], D[8 * v + 1]), b(D[8 * v + 2], D[8 * v + 3]);
+    const cd c(D[8 * v + 4], D[8 * v + 5]), d(D[8 * v + 6], D[8 * v + 7]);
+    const cd det = a * d - b * c;
+    if (det == cd(0.0, 0.0)) return USP_ERR_INVALID;
+    Di[4 * v + 0] = d / det;
+    Di[4 * v + 1] = -b / det;
+    Di[4 * v + 2] = -c / det;
+    Di[4 * v + 3] = a / det;
+  }
+  int rc = 0;
+  double mub[2], Rmu;
+  {
+    std::vector<double> pts(mu, mu + 2 * n);
+    circle_of(pts, mub, &Rmu, &rc);
+    if (rc) return rc;
+  }
+  cd dib[4];
+  double R2[4];
+  for (int e = 0; e < 4; ++e) {
+    std::vector<double> pts(2 * n);
+    for (size_t v = 0; v < n; ++v) {
+      pts[2 * v] = Di[4 * v + e].real();
+      pts[2 * v + 1] = Di[4 * v + e].imag();
+    }
+    double cc[2];
+    circle_of(pts, cc, &R2[e], &rc);
+    if (rc) return rc;
+    dib[e] = cd(cc[0], cc[1]);
+  }
+  // symmetric infinity-norm equilibration of the radii
+  const double dV[3][3] = {{Rmu, 0.0, 0.0}, {0.0, R2[0], R2[1]}, {0.0, R2[2], R2[3]}};
+  double s[3] = {1.0, 1.0, 1.0};
+  for (int sweep = 0; sweep < 50; ++sweep)
+    for (int i = 0; i < 3; ++i) {
+      double r = 0.0;
+      for (int j = 0; j < 3; ++j) r = std::max(r, s[i] * dV[i][j] * s[j]);
+      if (r > 0.0) s[i] /= std::sqrt(r);
+    }
+  // c = max over voxels of ||S V~ S||_2 / vnorm
+  const cd mubar(mub[0], mub[1]);
+  double vmax = 0.0;
+  auto v2 = [&](size_t v, int e) {
+    const int a = e / 2, b = e % 2;
+    return s[1 + a] * s[1 + b] * (Di[4 * v + e] - dib[e]);
+  };
+  for (size_t v = 0; v < n; ++v) {
+    const double vu = s[0] * s[0] * std::abs(cd(mu[2 * v], mu[2 * v + 1]) - mubar);
+    const cd m00 = v2(v, 0), m01 = v2(v, 1), m10 = v2(v, 2), m11 = v2(v, 3);
+    // largest eigenvalue of M^H M = [[p, q], [conj q, r]]
+    const double p = std::norm(m00) + std::norm(m10), r = std::norm(m01) + std::norm(m11);
+    const cd q = std::conj(m00) * m01 + std::conj(m10) * m11;
+    const double lmax = 0.5 * (p + r) + std::sqrt(0.25 * (p - r) * (p - r) + std::norm(q));
+    vmax = std::max(vmax, std::max(vu, std::sqrt(std::max(lmax, 0.0))));
+  }
+  double c = vmax / vnorm;
+  if (!(c > 0.0)) c = 1.0;
+  sym->n0 = n0;
+  sym->n1 = n1;
+  sym->h = h;
+  for (int k = 0; k < 3; ++k) sym->s[k] = s[k];
+  sym->c = c;
+  sym->mubar[0] = mub[0];
+  sym->mubar[1] = mub[1];
+  for (int e = 0; e < 4; ++e) {
+    sym->dibar[e][0] = dib[e].real();
+    sym->dibar[e][1] = dib[e].imag();
+  }
+  const double rsc = 1.0 / std::sqrt(c);
+  for (size_t v = 0; v < n; ++v) {
+    const cd bu = 1.0 - s[0] * s[0] * (cd(mu[2 * v], mu[2 * v + 1]) - mubar) / c;
+    bu_out[2 * v] = bu.real();
+    bu_out[2 * v + 1] = bu.imag();
+    for (int e = 0; e < 4; ++e) {
+      const cd b = ((e == 0 || e == 3) ? 1.0 : 0.0) - v2(v, e) / c;
+      b2_out[8 * v + 2 * e] = b.real();
+      b2_out[8 * v + 2 * e + 1] = b.imag();
+    }
+    y_out[2 * v] = s[0] * src[2 * v] * rsc;
+    y_out[2 * v + 1] = s[0] * src[2 * v + 1] * rsc;
+    y_out[2 * (n + v)] = y_out[2 * (n + v) + 1] = 0.0;
+    y_out[2 * (2 * n + v)] = y_out[2 * (2 * n + v) + 1] = 0.0;
+  }
   return 0;
 }

@@ -227,6 +227,37 @@ def diffusion_ring(n=256, h=0.1, D_bg=2.0, D_t=25.0, D_r=1.0, radius=7.0, width=
     return FluxDiffusionProblem(mu=mu, D=D, source=src, h=float(h))
 
 
+def diffusion_tensor_random(shape=(32, 128), seed=7, h=0.25, d_lo=0.5, d_hi=5.0, mu_lo=0.05, mu_hi=1.0,
+                            smooth=3.0):
+    """Random anisotropic medium on an (n0, n1) grid: per voxel D = R(theta) diag(d1, d2) R(theta)^T
+    with d1, d2 log-uniform in [d_lo, d_hi] and theta uniform, all three fields smoothed
+    (periodic Gaussian of `smooth` voxels) before mapping; absorption mu in [mu_lo, mu_hi] the
+    same way; a complex Gaussian random source."""
+    rng = np.random.default_rng(seed)
+    n0, n1 = shape
+
+    def field():
+        g = rng.normal(size=shape)
+        k0 = np.fft.fftfreq(n0)[:, None]
+        k1 = np.fft.fftfreq(n1)[None, :]
+        g = np.real(np.fft.ifft2(np.fft.fft2(g) * np.exp(-2 * (np.pi * smooth) ** 2 * (k0 ** 2 + k1 ** 2))))
+        g = (g - g.mean()) / (g.std() + 1e-300)
+        return 0.5 * (1.0 + np.tanh(g))          # in (0, 1)
+
+    d1 = d_lo * (d_hi / d_lo) ** field()
+    d2 = d_lo * (d_hi / d_lo) ** field()
+    th = np.pi * field()
+    c, s = np.cos(th), np.sin(th)
+    D = np.zeros((n0, n1, 2, 2), dtype=np.complex128)
+    D[..., 0, 0] = d1 * c * c + d2 * s * s
+    D[..., 0, 1] = (d1 - d2) * c * s
+    D[..., 1, 0] = D[..., 0, 1]
+    D[..., 1, 1] = d1 * s * s + d2 * c * c
+    mu = (mu_lo + (mu_hi - mu_lo) * field()).astype(np.complex128)
+    src = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    return FluxDiffusionProblem(mu=mu, D=D, source=src, h=float(h))
+
+
 def batch_sizes(nprob=96, seed=4, choices=(128, 256, 512, 1024)):
     """Side lengths of the batched 2-D problems, drawn uniformly from ``choices``."""
     rng = np.random.default_rng(seed)

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["Operator", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
+__all__ = ["Operator", "FluxOperator", "canonical_flux_host", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
            "canonical_diffusion", "canonical_pantograph", "canonical_fields"]
 
 
@@ -328,6 +328,94 @@ class Operator:
         L.check(L.lib().usp_residual(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), _dp(rel), _dp(rn),
                                      _dp(yn)))
         return float(rel[0]), float(rn[0]), float(yn[0])
+
+
+def canonical_flux_host(mu, D, source, h, vnorm: float = 0.95):
+    """usp_canonical_flux (host): returns (usp_flux_symbol, bu (n0, n1), b2 (n0, n1, 2, 2), y (3, n0, n1))."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.complex128))
+    Dm = np.ascontiguousarray(np.asarray(D, dtype=np.complex128))
+    src = np.ascontiguousarray(np.asarray(source, dtype=np.complex128))
+    n0, n1 = mu.shape
+    if Dm.shape != (n0, n1, 2, 2) or src.shape != (n0, n1):
+        raise ValueError("mu (n0, n1), D (n0, n1, 2, 2), source (n0, n1)")
+    sym = L.usp_flux_symbol()
+    bu = np.zeros((n0, n1), np.complex128)
+    b2 = np.zeros((n0, n1, 2, 2), np.complex128)
+    y = np.zeros((3, n0, n1), np.complex128)
+    f = lambda z: _dp(z.view(np.float64))
+    L.check(L.lib().usp_canonical_flux(f(mu), f(Dm), f(src), n0, n1, float(h), float(vnorm), ct.byref(sym),
+                                       f(bu), f(b2), f(y)))
+    return sym, bu, b2, y
+
+
+class FluxOperator:
+    """Steady diffusion in flux form with a tensor coefficient (usp_canonical_flux
+    on the host, then usp_flux_solve / usp_flux_residual on the device).
+    Fields are (3, n0, n1) tensors: [u; Jx; Jy] of the canonical system."""
+
+    def __init__(self, mu, D, source, h, vnorm: float = 0.95, dtype=torch.complex128, device="cuda"):
+        self.sym, bu, b2, y = canonical_flux_host(mu, D, source, h, vnorm)
+        n0, n1 = bu.shape
+        self.device = torch.device(device)
+        self.dtype = dtype
+        self.dt = L.USP_C64 if dtype == torch.complex64 else L.USP_C128
+        T = lambda z: torch.from_numpy(z).to(device=self.device, dtype=dtype)
+        self.bu, self.b2, self.y = T(bu), T(b2), T(y)
+        self.device = self.y.device          # "cuda" resolved to "cuda:<index>"
+        self.shape = (3, n0, n1)
+        nb = ct.c_size_t()
+        L.check(L.lib().usp_flux_workspace_bytes(ct.byref(self.sym), self.dt, ct.byref(nb)))
+        self.ws_bytes = nb.value
+        self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+
+    @property
+    def s(self):
+        return np.array(self.sym.s[:])
+
+    @property
+    def c(self):
+        return float(self.sym.c)
+
+    def _field(self, t):
+        if t.dtype != self.dtype or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != self.shape:
+            raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
+        return t
+
+    def solve(self, y=None, x=None, alpha=1.0, tol=1e-6, maxit=10000, check_every=20) -> SolveResult:
+        y = self.y if y is None else self._field(y)
+        guess = x is not None
+        x = self._field(x) if guess else torch.empty_like(y)
+        hp = np.zeros(max(maxit, 1))
+        ntc = maxit // check_every + 2
+        ht = np.zeros(2 * ntc)
+        it, nt = ct.c_int(), ct.c_int()
+        rc = L.check(L.lib().usp_flux_solve(ct.byref(self.sym), self.dt, _ptr(self.bu), _ptr(self.b2), _ptr(y),
+                                            _ptr(x), int(guess), float(alpha), float(tol), int(maxit),
+                                            int(check_every), _ptr(self.workspace), self.ws_bytes,
+                                            _stream_ptr(self.device), ct.byref(it), _dp(hp), maxit, _dp(ht), ntc,
+                                            ct.byref(nt)))
+        m = min(nt.value, ntc)
+        return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:min(it.value, maxit)].copy(),
+                           hist_true=ht[:2 * m].reshape(m, 2).copy())
+
+    def iterate(self, y=None, x=None, alpha=1.0, K=1):
+        """Exactly K iterations (no early stop); returns (x, ||Delta_i||^2 array)."""
+        r = self.solve(y, x, alpha=alpha, tol=-1.0, maxit=K, check_every=max(K, 1))
+        return r.x, r.hist_pre
+
+    def residual(self, x, y=None) -> float:
+        """FP64 ||y - A x|| / ||y||."""
+        y = self.y if y is None else self._field(y)
+        rel = np.zeros(1)
+        L.check(L.lib().usp_flux_residual(ct.byref(self.sym), self.dt, _ptr(self.bu), _ptr(self.b2), _ptr(y),
+                                          _ptr(self._field(x)), _ptr(self.workspace), self.ws_bytes,
+                                          _stream_ptr(self.device), _dp(rel)))
+        return float(rel[0])
+
+    def physical(self, x):
+        """[u; Jx; Jy] = S x / sqrt(c)."""
+        s = torch.tensor(self.s, dtype=torch.float64, device=x.device).to(x.real.dtype)
+        return x * (s[:, None, None] / np.sqrt(self.c))
 
 
 @dataclass

@@ -123,3 +123,34 @@ def test_host_canonical_pantograph_matches_oracle():
         assert np.allclose(So, Sl, atol=1e-10)
         co = solver.symbol_coeffs(sym)
         assert co["a1"] == 1 and sym.nyquist_zero == 1 and abs(co["s"] - cp.s) < 1e-12
+
+
+def test_host_canonical_flux_matches_oracle():
+    """Library flux-form canonicalisation (closed-form 2 x 2 spectral norms) vs
+    the oracle (numpy SVD norms), on the anisotropic ring and an isotropic case."""
+    import ctypes as ct
+    from oracle import flux as F
+    from paper_2207_14222_amd import _lib, media, solver
+    p = media.diffusion_ring(n=64, h=0.4, radius=8.0, width=3.0, abs_rows=6, src_row=3)
+    cases = [(p.mu, p.D, p.source, p.h)]
+    n = 16
+    Di = np.zeros((n, n, 2, 2), complex)
+    Di[..., 0, 0] = Di[..., 1, 1] = 1.7
+    mu = np.full((n, n), 0.3, complex)
+    mu[0, 0] = 2.0
+    cases.append((mu, Di, np.ones((n, n)), 0.5))
+    for mu, D, src, h in cases:
+        cp = F.canonical_flux(mu, D, src, h)
+        sym, bu, b2, y = solver.canonical_flux_host(mu, D, src, h)
+        assert abs(sym.c - cp.c) < 1e-12 * cp.c
+        assert np.allclose(np.array(sym.s[:]), cp.s, rtol=1e-12)
+        assert abs(complex(*sym.mubar) - cp.mubar) < 1e-12 * (1 + abs(cp.mubar))
+        dib = np.array([complex(*sym.dibar[e]) for e in range(4)]).reshape(2, 2)
+        assert np.allclose(dib, cp.Dibar, rtol=1e-12, atol=1e-14)
+        assert np.allclose(bu, cp.Buu, atol=1e-12) and np.allclose(b2, cp.B2, atol=1e-12)
+        assert np.allclose(y, cp.y, rtol=1e-12, atol=1e-14)
+    # a singular tensor is rejected
+    Ds = np.array(p.D, dtype=complex)
+    Ds[3, 3] = 0.0
+    with pytest.raises(_lib.UspError):
+        solver.canonical_flux_host(p.mu, Ds, p.source, p.h)
