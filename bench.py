@@ -17,7 +17,8 @@ plain complex64 solve's attainable residual, per-pass kernel times (hipEvents
 on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
 the other workloads under "modes": BiCGSTAB and GMRES(m) on the same
 preconditioned operator, the pantograph in direct and antisymmetrised
-form, diffusion (plain vs refined), 96 batched
+form, diffusion (plain vs refined), flux-form tensor diffusion on the
+256 x 256 ring, 96 batched
 2-D problems in one graph-captured schedule, and the learned initial guess
 on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
 protocol is 2000 / 200 media).
@@ -258,6 +259,44 @@ def bench_pantograph(args, log):
     return out
 
 
+def bench_flux(args, log):
+    """Steady anisotropic diffusion in flux form (Sec. 3.2) on the 256 x 256 ring:
+    complex128 and complex64 solves from x = 0 at alpha = 1 to ||r||/||y|| < 1e-3
+    (the tolerance of Table 1) and complex128 to 1e-6, the FP64 residual checked
+    every 10 iterations.  Bytes per iteration (two launches): the column pass
+    reads and writes the 3 planes of t (6 N values); the row pass reads t, x,
+    y, b_u, b2 (3+3+3+1+4 N) and writes x and t (6 N)."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    p = media.diffusion_ring(n=256)
+    n = p.mu.size
+    out = {}
+    for dname, dt, es in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        op = solver.FluxOperator(p.mu, p.D, p.source, p.h, dtype=dt)
+        iter_bytes = (6 + 20) * n * es
+        for tol in ((1e-3, 1e-6) if dname == "c128" else (1e-3,)):
+            op.solve(alpha=1.0, tol=tol, maxit=20000, check_every=10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = op.solve(alpha=1.0, tol=tol, maxit=20000, check_every=10)
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            # iteration cost without the residual checks
+            K = 200
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            op.iterate(alpha=1.0, K=K)
+            torch.cuda.synchronize()
+            us_it = (time.perf_counter() - t1) * 1e6 / K
+            out[f"{dname}_tol{tol:g}"] = {
+                "time_ms": round(dtm * 1e3, 3), "iterations": r.iterations, "status": r.status_name,
+                "rho": float(r.hist_true[-1, 1]), "us_per_iteration": round(us_it, 2),
+                "model_GB/s_per_iter": round(iter_bytes / (us_it * 1e-6) / 1e9, 1)}
+        del op
+    log(f"flux-form diffusion: {out}")
+    return out
+
+
 def bench_learned(args, log):
     """Learned initial guess on 128^3 random-sphere media (shared canonical scaling):
     training data from solves of the method (seeds 0..), Adam training of the
@@ -321,6 +360,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
     ap.add_argument("--batch-n", type=int, default=96)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess workload")
+    ap.add_argument("--no-flux", action="store_true", help="skip the flux-form tensor diffusion workload")
     ap.add_argument("--learned-train", type=int, default=600, help="training media (the full protocol uses 2000)")
     ap.add_argument("--learned-test", type=int, default=30, help="held-out media (the full protocol uses 200)")
     ap.add_argument("--learned-epochs", type=int, default=4)
@@ -460,6 +500,11 @@ def main():
     if not args.no_extra:
         log("diffusion workload")
         extra["diffusion"] = bench_diffusion(args, log)
+        torch.cuda.empty_cache()
+
+    if not args.no_flux:
+        log("flux-form tensor diffusion (256 x 256 ring)")
+        extra["flux_ring256"] = bench_flux(args, log)
         torch.cuda.empty_cache()
 
     if not args.no_batch:

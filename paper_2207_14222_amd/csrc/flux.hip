@@ -17,8 +17,8 @@ using namespace usp_detail;
 
 namespace {
 
-constexpr int kFxHist = 1 << 16;
-constexpr int kFxBlocks = 2048;
+constexpr int kFxHist = 1 << 16;   // device ring of ||Delta||^2 values
+constexpr int kFxRows = 32;        // ring of per-iteration partial rows, summed in batches
 
 struct FxLayout {
   size_t t = 0, S = 0, part = 0, hist = 0, scal = 0, tw0f = 0, tw0d = 0, tw1f = 0, tw1d = 0, total = 0;
@@ -34,6 +34,13 @@ int fx_check(const usp_flux_symbol* sym, int dtype) {
   return 0;
 }
 
+// blocks of the row kernel for a row length n1 (rows of n0)
+int fx_row_blocks(int n0, int n1) {
+  int lpb = 1;
+  with_n(n1, [&](auto NC) { lpb = FxRow<decltype(NC)::value>::LPB; });
+  return (n0 + lpb - 1) / lpb;
+}
+
 FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
   FxLayout L;
   const long N = (long)sym->n0 * sym->n1;
@@ -44,10 +51,10 @@ FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
     off = align_up(off + b);
     return o;
   };
-  L.pitch = std::min<long>((N + 255) / 256, kFxBlocks);
+  L.pitch = fx_row_blocks(sym->n0, sym->n1);
   L.t = take(3 * N * es);
   L.S = take(3 * N * 16);
-  L.part = take(sizeof(double) * 3 * L.pitch);
+  L.part = take(sizeof(double) * (kFxRows + 2) * L.pitch);
   L.hist = take(sizeof(double) * kFxHist);
   L.scal = take(sizeof(double) * 64);
   L.tw0f = take(sizeof(float2) * sym->n0);
@@ -60,14 +67,20 @@ FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
 
 FluxSym fx_sym(const usp_flux_symbol* s) {
   FluxSym f;
-  for (int k = 0; k < 3; ++k) f.s[k] = s->s[k];
-  f.c = s->c;
-  f.mubar[0] = s->mubar[0];
-  f.mubar[1] = s->mubar[1];
-  for (int k = 0; k < 4; ++k) {
-    f.dibar[k][0] = s->dibar[k][0];
-    f.dibar[k][1] = s->dibar[k][1];
-  }
+  const double ic = 1.0 / s->c;
+  f.A[0] = 1.0 + s->s[0] * s->s[0] * s->mubar[0] * ic;
+  f.A[1] = s->s[0] * s->s[0] * s->mubar[1] * ic;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const double w = s->s[1 + a] * s->s[1 + b] * ic;
+      f.E[2 * a + b][0] = (a == b ? 1.0 : 0.0) + w * s->dibar[2 * a + b][0];
+      f.E[2 * a + b][1] = w * s->dibar[2 * a + b][1];
+    }
+  const double(*E)[2] = f.E;
+  f.dE[0] = (E[0][0] * E[3][0] - E[0][1] * E[3][1]) - (E[1][0] * E[2][0] - E[1][1] * E[2][1]);
+  f.dE[1] = (E[0][0] * E[3][1] + E[0][1] * E[3][0]) - (E[1][0] * E[2][1] + E[1][1] * E[2][0]);
+  f.q1 = s->s[0] * s->s[1] * ic;
+  f.q2 = s->s[0] * s->s[2] * ic;
   f.pscale0 = 2.0 * M_PI / (s->n0 * s->h);
   f.pscale1 = 2.0 * M_PI / (s->n1 * s->h);
   f.n0 = s->n0;
@@ -82,7 +95,6 @@ struct FxRun {
   char* ws;
   hipStream_t st;
   long N;
-  int vb;
   template <class C> C* t() const { return (C*)(ws + L.t); }
   double2* S() const { return (double2*)(ws + L.S); }
   double* part() const { return (double*)(ws + L.part); }
@@ -118,64 +130,54 @@ int fx_twiddles(const FxRun& R) {
   return 0;
 }
 
-// forward (DIR -1) or inverse (+1) 2-D FFT of the 3 component planes of `d`
-template <class C, int DIR>
-int fx_fft2(const FxRun& R, C* d) {
-  const int n0 = R.sym->n0, n1 = R.sym->n1;
-  const int nlines = 3 * n0;
-  bool ok = true;
-  auto xpass = [&]() {
-    ok = with_n(n1, [&](auto NC) {
-      constexpr int N = decltype(NC)::value;
-      constexpr int TPB = x_threads<C>();
-      constexpr int LPB = TPB / (N / PassPlan<N>::E);
-      hipLaunchKernelGGL((k_xfft<C, N, DIR>), dim3((nlines + LPB - 1) / LPB), dim3(TPB), 0, R.st, d, R.tw1<C>(),
-                         nlines);
-    });
-  };
-  auto ypass = [&]() {
-    bool launched = false;
-    ok = with_n(n0, [&](auto NC) {
-      constexpr int N = decltype(NC)::value;
-      constexpr int E = PassPlan<N>::E;
-      auto go = [&](auto WC) {
-        constexpr int W = decltype(WC)::value;
-        if constexpr (s_width_ok<C>(N, W, E)) {
-          if (launched || n1 % W) return;
-          hipLaunchKernelGGL((k_spass<C, N, W, DIR < 0 ? S_FWD : S_INV>), dim3(n1 / W, 3), dim3(W * (N / E)), 0, R.st,
-                             d, R.tw0<C>(), (long)n1, SymArgs{});
-          launched = true;
-        }
-      };
-      go(std::integral_constant<int, 16>{});
-      go(std::integral_constant<int, 8>{});
-      go(std::integral_constant<int, 4>{});
-    });
-    ok = ok && launched;
-  };
-  if (DIR < 0) {
-    xpass();
-    if (ok) ypass();
-  } else {
-    ypass();
-    if (ok) xpass();
-  }
-  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux grid FFT plan");
-  LAUNCHCHK("flux fft");
+// y-axis pass with the per-mode block: (L + I)^-1 (inv) or L, on the 3 planes of d
+template <class C>
+int fx_col(const FxRun& R, C* d, bool inv) {
+  const bool ok = with_n(R.sym->n0, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    using G = FxCol<C, N>;
+    const dim3 grid((unsigned)(R.sym->n1 / G::W));
+    if (inv)
+      hipLaunchKernelGGL((k_fx_col<C, N, true>), grid, dim3(G::THREADS), 0, R.st, d, R.tw0<C>(), R.fs);
+    else
+      hipLaunchKernelGGL((k_fx_col<C, N, false>), grid, dim3(G::THREADS), 0, R.st, d, R.tw0<C>(), R.fs);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux column pass");
+  LAUNCHCHK("k_fx_col");
+  return 0;
+}
+
+// x-axis pass in the given mode
+template <class Cc, class Cx, int MODE>
+int fx_row(const FxRun& R, Cc* spec, Cx* x, const Cx* y, const Cx* bu, const Cx* b2, double alpha, int has_x,
+           double* row0, double* row1) {
+  const bool ok = with_n(R.sym->n1, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    hipLaunchKernelGGL((k_fx_row<Cc, Cx, N, MODE>), dim3((unsigned)R.L.pitch), dim3(3 * FxRow<N>::G), 0, R.st,
+                       spec, x, y, bu, b2, R.tw1<Cc>(), alpha, R.sym->n0, has_x, row0, row1);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux row pass");
+  LAUNCHCHK("k_fx_row");
+  return 0;
+}
+
+// ordered sums of `nrows` partial rows starting at ring row `first` into out
+int fx_sum(const FxRun& R, int first, int nrows, int ring, double* out, int out_first, int out_ring) {
+  if (nrows <= 0) return 0;
+  hipLaunchKernelGGL(k_fx_sum<0>, dim3(nrows), dim3(256), 0, R.st, R.part(), R.L.pitch, (int)R.L.pitch, first, ring,
+                     out, out_first, out_ring);
+  LAUNCHCHK("k_fx_sum");
   return 0;
 }
 
 template <class C>
 int fx_residual(const FxRun& R, const C* bu, const C* b2, const C* y, const C* x, double* rho) {
   int rc;
-  hipLaunchKernelGGL(k_fx_widen<C>, dim3(R.vb), dim3(256), 0, R.st, x, R.S(), 3 * R.N);
-  if ((rc = fx_fft2<double2, -1>(R, R.S()))) return rc;
-  hipLaunchKernelGGL(k_fx_sym<double2>, dim3(R.vb), dim3(256), 0, R.st, R.S(), R.fs, 0);
-  if ((rc = fx_fft2<double2, +1>(R, R.S()))) return rc;
-  hipLaunchKernelGGL(k_fx_res<C>, dim3(R.vb), dim3(256), 0, R.st, (const double2*)R.S(), x, y, bu, b2, R.N,
-                     R.part() + R.L.pitch, R.part() + 2 * R.L.pitch);
-  hipLaunchKernelGGL(k_fx_sum<0>, dim3(2), dim3(256), 0, R.st, R.part() + R.L.pitch, R.L.pitch, R.vb, R.scal());
-  LAUNCHCHK("flux residual");
+  double* r0 = R.part() + kFxRows * R.L.pitch;
+  if ((rc = fx_row<double2, C, FX_RFWD>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, nullptr, nullptr))) return rc;
+  if ((rc = fx_col<double2>(R, R.S(), false))) return rc;
+  if ((rc = fx_row<double2, C, FX_RINV>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, r0, r0 + R.L.pitch))) return rc;
+  if ((rc = fx_sum(R, kFxRows, 2, kFxRows + 2, R.scal(), 0, 2))) return rc;
   double h[2];
   HIPCHK(hipMemcpyAsync(h, R.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, R.st));
   HIPCHK(hipStreamSynchronize(R.st));
@@ -190,11 +192,17 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
   int rc;
   C* t = R.t<C>();
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * 3 * R.N, R.st));
-  hipLaunchKernelGGL(k_fx_first<C>, dim3(R.vb), dim3(256), 0, R.st, (const C*)x, y, bu, b2, t, R.N, x_is_guess ? 1 : 0);
-  LAUNCHCHK("k_fx_first");
-  int it = 0, ntrue = 0, status = USP_MAXIT, pulled = 0, grow = 0;
+  if ((rc = fx_row<C, C, FX_FIRST>(R, t, x, y, bu, b2, 0.0, x_is_guess ? 1 : 0, nullptr, nullptr))) return rc;
+  int it = 0, ntrue = 0, status = USP_MAXIT, pulled = 0, flushed = 0, grow = 0;
   double d0 = -1.0, dprev = -1.0;
   std::vector<double> buf;
+  // sum the pending partial rows of iterations [flushed, it) into the history ring
+  auto flush = [&]() -> int {
+    const int m = it - flushed;
+    const int e = fx_sum(R, flushed % kFxRows, m, kFxRows, R.hist(), flushed % kFxHist, kFxHist);
+    flushed = it;
+    return e;
+  };
   auto pull = [&]() -> int {
     const int n = it - pulled;
     if (n <= 0) return 0;
@@ -219,16 +227,15 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
     return 0;
   };
   while (it < maxit) {
-    if ((rc = fx_fft2<C, -1>(R, t))) return rc;
-    hipLaunchKernelGGL(k_fx_sym<C>, dim3(R.vb), dim3(256), 0, R.st, t, R.fs, 1);
-    if ((rc = fx_fft2<C, +1>(R, t))) return rc;
-    hipLaunchKernelGGL(k_fx_update<C>, dim3(R.vb), dim3(256), 0, R.st, t, x, y, bu, b2, alpha, R.N, R.part());
-    hipLaunchKernelGGL(k_fx_sum<0>, dim3(1), dim3(256), 0, R.st, R.part(), R.L.pitch, R.vb, R.hist() + it % kFxHist);
-    LAUNCHCHK("flux iteration");
+    if ((rc = fx_col<C>(R, t, true))) return rc;
+    if ((rc = fx_row<C, C, FX_FUSED>(R, t, x, y, bu, b2, alpha, 1, R.part() + (it % kFxRows) * R.L.pitch,
+                                     nullptr)))
+      return rc;
     ++it;
+    if (it - flushed == kFxRows && (rc = flush())) return rc;
     const bool chk = it % check_every == 0 || it == maxit;
     if (chk || it - pulled >= kFxHist / 2) {
-      if ((rc = pull())) return rc;
+      if ((rc = flush()) || (rc = pull())) return rc;
       if (status == USP_ERR_NAN || status == USP_DIVERGED) break;
     }
     if (chk) {
@@ -243,7 +250,7 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
       if (rho < tol) { status = USP_OK; break; }
     }
   }
-  if ((rc = pull())) return rc;
+  if ((rc = flush()) || (rc = pull())) return rc;
   if (iters_out) *iters_out = it;
   if (n_true_out) *n_true_out = ntrue;
   if (status < 0) return fail(status, "non-finite values in the iteration");
@@ -262,7 +269,6 @@ int fx_begin(const usp_flux_symbol* sym, int dtype, void* ws, size_t ws_bytes, v
   R->ws = (char*)ws;
   R->st = (hipStream_t)stream;
   R->N = (long)sym->n0 * sym->n1;
-  R->vb = (int)R->L.pitch;
   return fx_twiddles(*R);
 }
 

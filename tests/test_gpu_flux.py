@@ -4,8 +4,8 @@ FP64 oracle:
 
 * K iterates of Algorithm 1 and ||Delta_i|| (complex128 1e-11, complex64 3e-5)
   on the anisotropic ring (64 x 64, and the 256 x 256 workload) and on random
-  tensor media with non-square grids (lengths 8 to 1024 on either axis, the
-  strided pass with one 8-column tile at n1 = 8);
+  tensor media with non-square grids (lengths 8 to 1024 on either axis:
+  every column-tile width and both twiddle placements of the column pass);
 * the FP64 residual of an arbitrary x against the oracle's (1e-12);
 * the solve reaches the dense-LU solution on a 16 x 16 grid (768 unknowns)
   and the Schur reduction holds for the physical u;
@@ -41,7 +41,7 @@ def _medium(name):
     if name == "ring16":
         return media.diffusion_ring(n=16, h=0.6, radius=3.0, width=1.5, abs_rows=3, src_row=2)
     shape = {"rand32x128": (32, 128), "rand128x8": (128, 8), "rand512x16": (512, 16),
-             "rand16x1024": (16, 1024)}[name]
+             "rand16x1024": (16, 1024), "rand1024x8": (1024, 8), "rand8x512": (8, 512)}[name]
     return media.diffusion_tensor_random(shape=shape, seed=sum(shape))
 
 
@@ -52,7 +52,8 @@ def _pair(p, dtype=torch.complex128):
     return cp, F.FluxOperator(cp), gop
 
 
-@pytest.mark.parametrize("name", ["ring64", "rand32x128", "rand128x8", "rand512x16", "rand16x1024", "ring256"])
+@pytest.mark.parametrize("name", ["ring64", "rand32x128", "rand128x8", "rand512x16", "rand16x1024", "rand1024x8",
+                                  "rand8x512", "ring256"])
 @pytest.mark.parametrize("dt", ["c128", "c64"])
 def test_iterates_match_oracle(name, dt):
     _need_gpu()
