@@ -20,9 +20,12 @@ computes, written from the paper:
                     per-voxel blocks of V, equilibration and scaling.
 * ``antisym``    -- the antisymmetrised canonical form for systems that are
                     not accretive (Sec. 2.2), built on a 1-D operator.
-* ``krylov``     -- BiCGSTAB and restarted GMRES(m) on the preconditioned
+* ``krylov``     -- BiCGSTAB, restarted GMRES(m) and CG on the preconditioned
                     operator with the forward problem eliminated (the solver
                     comparison of Sec. 4, Table 1b).
+* ``eigen``      -- lowest-energy Schrodinger eigenmodes with the shifted,
+                    canonical operator (Sec. 4, Eq. schrodinger): dense
+                    definition, energies, residuals, condition numbers.
 * ``surrogate``  -- the learned initial guess's network, loss, input channels
                     and Adam in plain PyTorch CPU float64.
 * ``theory``     -- dense-matrix quantities of the appendix theorems

@@ -1,6 +1,10 @@
 """Krylov drivers on the preconditioned system with the forward problem
 eliminated (Sec. 2.1; the solver comparison of Sec. 4, Table 1b): BiCGSTAB
-(van der Vorst, 1992) and restarted GMRES(m) (Saad and Schultz, 1986).
+(van der Vorst, 1992), restarted GMRES(m) (Saad and Schultz, 1986) and, for
+Hermitian positive definite A (the eigenmode example of Sec. 4, whose linear
+solves use conjugate gradients), CG (Hestenes and Stiefel, 1952): with A, L
+and V Hermitian, P = B - B (L + I)^-1 B is Hermitian, and P = B [B^-1 -
+(L + I)^-1] B is positive definite when A = L + I - B is (B is, as ||V|| < 1).
 
 TEST INFRASTRUCTURE (FP64 oracle) -- see ``oracle/__init__.py``.
 
@@ -86,6 +90,38 @@ def bicgstab(op: Operator, y, tol, maxit, check_every=1, x0=None) -> KrylovResul
         r = s - omega * t
         rho = rho_new
         res.iterations = i + 1
+        if (i + 1) % check_every == 0 or i + 1 == maxit:
+            rho_t = _rel_true(op, x, y)
+            res.hist_true.append((i + 1, rho_t))
+            if rho_t < tol:
+                res.converged = True
+                break
+    res.x = x
+    return res
+
+
+def cg(op: Operator, y, tol, maxit, check_every=1, x0=None) -> KrylovResult:
+    """Conjugate gradients on P x = b (P Hermitian positive definite)."""
+    x = np.zeros(op.shape, dtype=np.complex128) if x0 is None else np.array(x0, dtype=np.complex128)
+    b = precond_rhs(op, y)
+    r = b - precond_apply(op, x)
+    p = r.copy()
+    rr = float(np.vdot(r, r).real)
+    res = KrylovResult(x=x, iterations=0)
+    for i in range(maxit):
+        q = precond_apply(op, p)
+        pq = np.vdot(p, q)
+        if pq == 0:
+            res.breakdown = True
+            break
+        alpha = rr / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = float(np.vdot(r, r).real)
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        res.iterations = i + 1
+        res.hist_est.append((i + 1, float(np.sqrt(rr))))
         if (i + 1) % check_every == 0 or i + 1 == maxit:
             rho_t = _rel_true(op, x, y)
             res.hist_true.append((i + 1, rho_t))

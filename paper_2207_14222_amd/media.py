@@ -258,6 +258,35 @@ def diffusion_tensor_random(shape=(32, 128), seed=7, h=0.25, d_lo=0.5, d_hi=5.0,
     return FluxDiffusionProblem(mu=mu, D=D, source=src, h=float(h))
 
 
+def double_ring_well(n=512, box=6.0, depth=10.0, diameter=2.0, width=0.2, gap=0.1):
+    """Potential well of two rings side by side (the eigenmode example): V = -depth on
+    two annuli of the given diameter and width whose outer edges are `gap` apart along
+    axis 1, 0 elsewhere, on an n x n grid covering [-box/2, box/2)^2.  Returns (V, h)."""
+    h = box / n
+    c = (np.arange(n) - n / 2) * h
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    R = 0.5 * diameter
+    off = R + 0.5 * width + 0.5 * gap
+    V = np.zeros((n, n))
+    for sx in (-1.0, 1.0):
+        r = np.hypot(xx - sx * off, yy)
+        V[np.abs(r - R) < 0.5 * width] = -depth
+    return V, h
+
+
+def harmonic_well(n=40, h=0.45, omega=1.0):
+    """V = omega^2 r^2 / 2 about the grid centre on an n x n grid.  Returns (V, h)."""
+    c = (np.arange(n) - n / 2) * h
+    yy, xx = np.meshgrid(c, c, indexing="ij")
+    return 0.5 * omega ** 2 * (xx ** 2 + yy ** 2), h
+
+
+def random_start(shape, seed=0):
+    """Seeded complex Gaussian start vector."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
 def batch_sizes(nprob=96, seed=4, choices=(128, 256, 512, 1024)):
     """Side lengths of the batched 2-D problems, drawn uniformly from ``choices``."""
     rng = np.random.default_rng(seed)
