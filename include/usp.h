@@ -388,6 +388,7 @@ int usp_flux_residual(const usp_flux_symbol* sym, int dtype, const void* bu_dev,
  * the handle's dtype, dot products and scalars are double. */
 #define USP_KRYLOV_BICGSTAB 1
 #define USP_KRYLOV_GMRES 2
+#define USP_KRYLOV_CG 3       /* Hermitian handles (real symbol and B); P is then Hermitian (positive definite when A is) */
 
 /* Workspace (device, 256-B aligned, caller-owned) of usp_solve_krylov for a
  * method (restart: GMRES cycle length in [1, 64]; ignored for BiCGSTAB):
@@ -415,6 +416,43 @@ int usp_apply_precond(usp_op op, const void* v_dev, void* w_dev, int rhs, void* 
 int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void* x_dev, int x_is_guess, double tol,
                      int maxit, int check_every, void* workspace_dev, size_t workspace_bytes, int* iters_out,
                      double* hist_est, int hist_est_cap, double* hist_true, int hist_true_cap, int* n_true_out);
+
+/* ---- eigenmodes (Sec. 4, Eq. schrodinger) -----------------------------------
+ *
+ * Lowest eigenpairs of a Hermitian canonical operator A (real symbol and real
+ * B: e.g. H + Abar = -1/2 laplacian + V + Abar prepared with
+ * usp_canonical_diffusion, D = 1/2, mu = V + Abar, omega = 0; then
+ * E = c lam - Abar).  Shift-invert Lanczos: the Krylov space of A^-1, each
+ * product A^-1 v by CG on the preconditioned system (to inner_tol relative
+ * residual of A w = v, at most inner_maxit iterations), full
+ * reorthogonalisation (classical Gram-Schmidt twice), thick restart keeping
+ * nev + (ncv - nev)/2 Ritz vectors (the Hermitian counterpart of an
+ * implicit restart).  A Ritz pair has converged when ||A u - lam u|| /
+ * ||lam u|| (FP64 residual passes) is below tol. */
+#define USP_EIGS_MAX_NEV 16
+#define USP_EIGS_MAX_NCV 64
+
+/* Workspace of usp_eigs: the CG vectors, ncv + 1 basis vectors, one work
+ * vector and ncv restart vectors of the handle's dtype.  nev in [1, 16],
+ * ncv in [nev + 2, 64]. */
+int usp_eigs_workspace_bytes(usp_op op, int nev, int ncv, size_t* bytes);
+
+/* v0_dev: start vector (N values, not all zero).  evecs_dev: nev vectors of
+ * N values (contiguous), unit norm, for evals_out (host, ascending
+ * eigenvalues of A); resid_out (host) their relative residuals.  Returns
+ * USP_OK when all nev pairs converged within max_restarts restarts, else
+ * USP_MAXIT (the best pairs are returned); USP_ERR_INVALID for a
+ * non-Hermitian handle.  restarts_out: restarts used; inner_iters_out: CG
+ * iterations summed over all inner solves (each one application of P). */
+int usp_eigs(usp_op op, int nev, int ncv, const void* v0_dev, double tol, int max_restarts, double inner_tol,
+             int inner_maxit, void* evecs_dev, double* evals_out, double* resid_out, void* ws_dev, size_t ws_bytes,
+             int* restarts_out, int* inner_iters_out);
+
+/* Host helper: eigenvalues (ascending, w_out[n]) and orthonormal eigenvectors
+ * (columns of z_out, n x n complex row-major, 2 n^2 doubles) of the Hermitian
+ * part of the n x n complex matrix a (row-major, 2 n^2 doubles), by cyclic
+ * Jacobi rotations; n <= 256.  Used for the Rayleigh-Ritz step of usp_eigs. */
+int usp_hermitian_eig(int n, const double* a, double* w_out, double* z_out);
 
 /* ---- learned initial guess: 3-D convolutional network kernels ----------
  *

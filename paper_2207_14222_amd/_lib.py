@@ -19,7 +19,7 @@ USP_C64, USP_C128 = 0, 1
 USP_FLAG_REFINE = 1
 USP_FLAG_ANTISYM = 2
 USP_BIAS_COMPLEX, USP_BIAS_REAL = 0, 1
-USP_KRYLOV_BICGSTAB, USP_KRYLOV_GMRES = 1, 2
+USP_KRYLOV_BICGSTAB, USP_KRYLOV_GMRES, USP_KRYLOV_CG = 1, 2, 3
 
 STATUS_NAMES = {0: "converged", 1: "maxit", 2: "stagnated", 3: "diverged", -1: "invalid",
                 -2: "unsupported_shape", -3: "not_contractive", -4: "hip_error", -5: "nan", -6: "workspace"}
@@ -32,7 +32,8 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_nn_pool2", "usp_nn_upsample2", "usp_nn_channel_copy", "usp_nn_relu_backward", "usp_nn_add",
            "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_pack_weights", "usp_nn_to_bf16",
            "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond",
-           "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual"]
+           "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual",
+           "usp_eigs_workspace_bytes", "usp_eigs", "usp_hermitian_eig"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -125,6 +126,9 @@ def lib():
     L.usp_krylov_workspace_bytes.argtypes = [P, I, I, ct.POINTER(ct.c_size_t)]
     L.usp_apply_precond.argtypes = [P, P, P, I, P, ct.c_size_t]
     L.usp_solve_krylov.argtypes = [P, I, I, P, P, I, D, I, I, P, ct.c_size_t, IP, DP, I, DP, I, IP]
+    L.usp_eigs_workspace_bytes.argtypes = [P, I, I, ct.POINTER(ct.c_size_t)]
+    L.usp_eigs.argtypes = [P, I, I, P, D, I, D, I, P, DP, DP, P, ct.c_size_t, IP, IP]
+    L.usp_hermitian_eig.argtypes = [I, DP, DP, DP]
     FS = ct.POINTER(usp_flux_symbol)
     L.usp_canonical_flux.argtypes = [DP, DP, DP, I, I, D, D, FS, DP, DP, DP]
     L.usp_flux_workspace_bytes.argtypes = [FS, I, ct.POINTER(ct.c_size_t)]

@@ -507,7 +507,8 @@ struct KWork {
 int krylov_layout(usp_op op, int method, int restart, KWork* kw) {
   if (op->d.ndim < 2 || op->has_gather) return fail(USP_ERR_UNSUPPORTED_SHAPE, "Krylov drivers need a 2-D or 3-D grid");
   if (op->refine) return fail(USP_ERR_INVALID, "Krylov drivers need a plain (not refined) handle");
-  if (method != USP_KRYLOV_BICGSTAB && method != USP_KRYLOV_GMRES) return fail(USP_ERR_INVALID, "unknown method");
+  if (method != USP_KRYLOV_BICGSTAB && method != USP_KRYLOV_GMRES && method != USP_KRYLOV_CG)
+    return fail(USP_ERR_INVALID, "unknown method");
   if (method == USP_KRYLOV_GMRES && (restart < 1 || restart > kMaxRestart))
     return fail(USP_ERR_INVALID, "restart must be in [1, 64]");
   const size_t es = op->dtype == USP_C64 ? 8 : 16;
@@ -516,8 +517,8 @@ int krylov_layout(usp_op op, int method, int restart, KWork* kw) {
   const long mb = (N + 256L * kMdotKE - 1) / (256L * kMdotKE);
   kw->N = N;
   kw->pitch = std::max<long>(std::max<long>(xb, mb), kVecBlocks);
-  kw->nvec = method == USP_KRYLOV_BICGSTAB ? 6 : restart + 3;
-  kw->nrows = method == USP_KRYLOV_BICGSTAB ? 5 : std::max(5, 2 * (restart + 1));
+  kw->nvec = method == USP_KRYLOV_BICGSTAB ? 6 : method == USP_KRYLOV_CG ? 3 : restart + 3;
+  kw->nrows = method == USP_KRYLOV_GMRES ? std::max(5, 2 * (restart + 1)) : 5;
   kw->vec_bytes = align_up(N * es);
   kw->total = kw->vec_bytes * kw->nvec + align_up(sizeof(double) * kw->nrows * kw->pitch) + sizeof(double) * kKsDoubles;
   return 0;
@@ -653,6 +654,61 @@ int solve_bicgstab(usp_op op, const C* y, C* x, int x_is_guess, double tol, int 
   return status;
 }
 
+// Conjugate gradients on P x = b for a Hermitian canonical operator (A, L, V
+// Hermitian; P is then Hermitian, and positive definite when A is).  Scalars
+// stay on the device; the host synchronises at true-residual checks only.
+template <class C>
+int solve_cg(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit, int check_every, const KWork& kw,
+             int* iters_out, Monitor& mon) {
+  const long n = op->d.N;
+  C *r = kw.vec<C>(0), *p = kw.vec<C>(1), *q = kw.vec<C>(2);
+  double* ks = kw.ks;
+  const int vb = vec_blocks(n);
+  const int xb = x_blocks<C>(op);
+  int rc;
+  if ((rc = norm2(op, y, op->scal + 1))) return rc;
+  HIPCHK(hipMemsetAsync(ks, 0, sizeof(double) * 32, op->st));
+  if ((rc = kapply<C>(op, y, r, true, nullptr, 0, kw))) return rc;   // r = b
+  if (x_is_guess) {
+    if ((rc = kapply<C>(op, x, q, false, nullptr, 0, kw))) return rc;
+    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, (const C*)q, n, kw.rows);
+    LAUNCHCHK("k_ksub");                                              // p = b - P x
+    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_CRR))) return rc;
+    HIPCHK(hipMemcpyAsync(r, p, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+  } else {
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * n, op->st));
+    if ((rc = norm2(op, (const C*)r, ks + KS_CRR))) return rc;
+    HIPCHK(hipMemcpyAsync(p, r, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+  }
+  int it = 0, status = USP_MAXIT;
+  while (it < maxit) {
+    if ((rc = kapply<C>(op, p, q, false, p, 1, kw))) return rc;           // q = P p, <p, q>
+    if ((rc = ksum(op, kw, 0, 2, xb, ks + KS_CPQ))) return rc;
+    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_CG_ALPHA);
+    hipLaunchKernelGGL(k_cg_x<C>, dim3(vb), dim3(256), 0, op->st, x, r, (const C*)p, (const C*)q, ks, n, kw.rows);
+    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_CRRN))) return rc;
+    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_CG_BETA);
+    hipLaunchKernelGGL(k_cg_p<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, ks, n);
+    LAUNCHCHK("cg iteration");
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      double rho, hk[2];
+      if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
+      HIPCHK(hipMemcpyAsync(hk, ks + KS_FLAG, sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipMemcpyAsync(hk + 1, ks + KS_CRR, sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipStreamSynchronize(op->st));
+      mon.delta(it - 1, hk[1]);
+      const bool stag = mon.check(it, rho);
+      if (mon.nan) { status = USP_ERR_NAN; break; }
+      if (rho < tol) { status = USP_OK; break; }
+      if (hk[0] > 0.0 || stag) { status = USP_STAGNATED; break; }   // breakdown or no progress
+    }
+  }
+  if (iters_out) *iters_out = it;
+  if (status < 0) return fail(status, "non-finite values in the iteration");
+  return status;
+}
+
 template <class C>
 int solve_gmres(usp_op op, const C* y, C* x, int x_is_guess, int m, double tol, int maxit, const KWork& kw,
                 int* iters_out, Monitor& mon) {
@@ -768,6 +824,253 @@ int solve_gmres(usp_op op, const C* y, C* x, int x_is_guess, int m, double tol, 
   if (iters_out) *iters_out = total;
   if (status < 0) return fail(status, "non-finite values in the iteration");
   return status;
+}
+
+// ---- eigenmodes: shift-invert Lanczos with thick restart ---------------------
+
+typedef std::complex<double> zd;
+
+// Eigen-decomposition of a Hermitian n x n matrix (row-major) by cyclic Jacobi
+// sweeps: each step turns a_pq real by a phase on column/row q, then zeroes it
+// with a real plane rotation.  w ascending, Z columns orthonormal eigenvectors.
+int hermitian_jacobi(int n, std::vector<zd> a, std::vector<double>& w, std::vector<zd>& Z) {
+  Z.assign((size_t)n * n, zd(0.0));
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  auto A = [&](int i, int j) -> zd& { return a[(size_t)i * n + j]; };
+  double scale = 0.0;
+  for (const zd& v : a) scale = std::max(scale, std::abs(v));
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off = std::max(off, std::abs(A(p, q)));
+    if (!(off > 1e-15 * scale)) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double g = std::abs(A(p, q));
+        if (!(g > 1e-300)) continue;
+        // phase: column q times e, row q times conj(e), so that a_pq becomes |a_pq|
+        const zd e = std::conj(A(p, q)) / g;
+        for (int k = 0; k < n; ++k) A(k, q) *= e;
+        for (int k = 0; k < n; ++k) A(q, k) *= std::conj(e);
+        for (int k = 0; k < n; ++k) Z[(size_t)k * n + q] *= e;
+        // real rotation on (p, q) zeroing the (now real) a_pq
+        const double app = A(p, p).real(), aqq = A(q, q).real(), apq = A(p, q).real();
+        const double th = (aqq - app) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {   // columns p, q
+          const zd kp = A(k, p), kq = A(k, q);
+          A(k, p) = c * kp - sn * kq;
+          A(k, q) = sn * kp + c * kq;
+        }
+        for (int k = 0; k < n; ++k) {   // rows p, q
+          const zd pk = A(p, k), qk = A(q, k);
+          A(p, k) = c * pk - sn * qk;
+          A(q, k) = sn * pk + c * qk;
+        }
+        A(p, q) = A(q, p) = 0.0;
+        for (int k = 0; k < n; ++k) {
+          const zd kp = Z[(size_t)k * n + p], kq = Z[(size_t)k * n + q];
+          Z[(size_t)k * n + p] = c * kp - sn * kq;
+          Z[(size_t)k * n + q] = sn * kp + c * kq;
+        }
+      }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::sort(idx.begin(), idx.end(), [&](int i, int j) { return A(i, i).real() < A(j, j).real(); });
+  std::vector<zd> Zs((size_t)n * n);
+  w.resize(n);
+  for (int jj = 0; jj < n; ++jj) {
+    w[jj] = A(idx[jj], idx[jj]).real();
+    for (int k = 0; k < n; ++k) Zs[(size_t)k * n + jj] = Z[(size_t)k * n + idx[jj]];
+  }
+  Z.swap(Zs);
+  return 0;
+}
+
+struct EigWork {
+  KWork kw;            // CG inner solves
+  size_t basis = 0, w = 0, tmp = 0, total = 0;
+  int ncv = 0;
+};
+
+int eigs_layout(usp_op op, int nev, int ncv, EigWork* ew) {
+  if (nev < 1 || nev > USP_EIGS_MAX_NEV) return fail(USP_ERR_INVALID, "nev must be in [1, 16]");
+  if (ncv < nev + 2 || ncv > USP_EIGS_MAX_NCV) return fail(USP_ERR_INVALID, "ncv must be in [nev + 2, 64]");
+  int rc = krylov_layout(op, USP_KRYLOV_CG, 0, &ew->kw);
+  if (rc) return rc;
+  // partial rows for the Gram-Schmidt dot products (2 per basis vector)
+  KWork& kw = ew->kw;
+  kw.nrows = std::max(kw.nrows, 2 * (ncv + 1));
+  kw.total = kw.vec_bytes * kw.nvec + align_up(sizeof(double) * kw.nrows * kw.pitch) + sizeof(double) * kKsDoubles;
+  const size_t vb = ew->kw.vec_bytes;
+  ew->ncv = ncv;
+  ew->basis = align_up(ew->kw.total);
+  ew->w = ew->basis + vb * (ncv + 1);
+  ew->tmp = ew->w + vb;
+  ew->total = ew->tmp + vb * ncv;
+  return 0;
+}
+
+template <class C>
+int eigs_run(usp_op op, int nev, int ncv, const C* v0, double tol, int max_restarts, double inner_tol, int inner_maxit,
+             C* evecs, double* evals, double* resid, char* ws, const EigWork& ew, int* restarts_out,
+             int* inner_out) {
+  const long n = op->d.N;
+  const KWork& kw = ew.kw;
+  const size_t vbytes = kw.vec_bytes;
+  const long stride = (long)(vbytes / sizeof(C));
+  C* V = (C*)(ws + ew.basis);
+  C* w = (C*)(ws + ew.w);
+  C* T = (C*)(ws + ew.tmp);
+  auto basis = [&](int i) { return (C*)((char*)V + (size_t)i * vbytes); };
+  auto tmpv = [&](int i) { return (C*)((char*)T + (size_t)i * vbytes); };
+  double* ks = kw.ks;
+  double* h1 = ks + KS_H;
+  double* h2 = h1 + 2 * (ncv + 1);
+  double* coef = ks + KS_COEF;
+  const int vb = vec_blocks(n);
+  const int mb = (int)((n + 256L * kMdotKE - 1) / (256L * kMdotKE));
+  const C* B = (const C*)op->B;
+  int rc;
+  // the handle must be Hermitian: real symbol, real B
+  {
+    const double sa0i = op->sa0[1], sa2i = op->sa2[1];
+    if (std::fabs(sa0i) > 1e-14 * (std::fabs(op->sa0[0]) + 1e-300) ||
+        std::fabs(sa2i) > 1e-14 * (std::fabs(op->sa2[0]) + 1e-300))
+      return fail(USP_ERR_INVALID, "eigenmodes need a Hermitian operator (real symbol)");
+    hipLaunchKernelGGL(k_imag2<C>, dim3(vb), dim3(256), 0, op->st, B, n, kw.rows);
+    LAUNCHCHK("k_imag2");
+    double im2 = 0.0;
+    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_NRM))) return rc;
+    HIPCHK(hipMemcpyAsync(&im2, ks + KS_NRM, sizeof(double), hipMemcpyDeviceToHost, op->st));
+    HIPCHK(hipStreamSynchronize(op->st));
+    if (im2 != 0.0) return fail(USP_ERR_INVALID, "eigenmodes need a Hermitian operator (real B)");
+  }
+  // v_0 = v0 / ||v0||
+  if ((rc = norm2(op, v0, ks + KS_NRM))) return rc;
+  hipLaunchKernelGGL(k_kscale<C>, dim3(vb), dim3(256), 0, op->st, basis(0), v0, n, (const double*)(ks + KS_NRM));
+  LAUNCHCHK("k_kscale");
+  std::vector<zd> H((size_t)(ncv + 1) * ncv, zd(0.0));
+  auto Hm = [&](int i, int j) -> zd& { return H[(size_t)i * ncv + j]; };
+  std::vector<double> hh(4 * (ncv + 1) + 1), cbuf(2 * ncv);
+  std::vector<double> theta;
+  std::vector<zd> S;
+  int k = 0, total_inner = 0, cycle = 0, m = ncv;
+  bool done = false;
+  double beta_last = 0.0;
+  std::vector<int> order(ncv);
+  // u = sum_i c_i basis(i) for i < m (c on the host, complex), written to out
+  auto combine = [&](const zd* c, int stride_c, C* out) -> int {
+    for (int i = 0; i < m; ++i) {
+      cbuf[2 * i] = c[(size_t)i * stride_c].real();
+      cbuf[2 * i + 1] = c[(size_t)i * stride_c].imag();
+    }
+    HIPCHK(hipMemcpyAsync(coef, cbuf.data(), sizeof(double) * 2 * m, hipMemcpyHostToDevice, op->st));
+    HIPCHK(hipMemsetAsync(out, 0, sizeof(C) * n, op->st));
+    hipLaunchKernelGGL(k_maxpy<C>, dim3(vb), dim3(256), 0, op->st, out, (const C*)V, stride, n, m, (const double*)coef,
+                       1.0, (double*)nullptr);
+    LAUNCHCHK("k_maxpy");
+    HIPCHK(hipStreamSynchronize(op->st));   // cbuf is reused by the next call
+    return 0;
+  };
+  for (cycle = 0; cycle <= max_restarts && !done; ++cycle) {
+    m = ncv;
+    for (int j = k; j < ncv; ++j) {
+      // w = A^-1 v_j (CG on P w = B (L + I)^-1 v_j from w = 0)
+      Monitor imon{nullptr, 0, nullptr, 0};
+      int its = 0;
+      rc = solve_cg<C>(op, basis(j), w, 0, inner_tol, inner_maxit, 10, kw, &its, imon);
+      total_inner += its;
+      if (rc < 0) return rc;
+      // classical Gram-Schmidt against v_0 .. v_j, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        double* hc = pass == 0 ? h1 : h2;
+        hipLaunchKernelGGL((k_mdot<C, kMdotKE>), dim3(mb), dim3(256), 0, op->st, (const C*)V, stride, n, j + 1,
+                           (const C*)w, kw.rows, kw.pitch);
+        if ((rc = ksum(op, kw, 0, 2 * (j + 1), mb, hc))) return rc;
+        hipLaunchKernelGGL(k_maxpy<C>, dim3(vb), dim3(256), 0, op->st, w, (const C*)V, stride, n, j + 1,
+                           (const double*)hc, -1.0, pass == 1 ? kw.rows : nullptr);
+      }
+      LAUNCHCHK("lanczos orthogonalisation");
+      if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_NRM))) return rc;
+      HIPCHK(hipMemcpyAsync(hh.data(), h1, sizeof(double) * 4 * (ncv + 1), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipMemcpyAsync(hh.data() + 4 * (ncv + 1), ks + KS_NRM, sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipStreamSynchronize(op->st));
+      for (int i = 0; i <= j; ++i)
+        Hm(i, j) = zd(hh[2 * i] + hh[2 * (ncv + 1) + 2 * i], hh[2 * i + 1] + hh[2 * (ncv + 1) + 2 * i + 1]);
+      const double bn = std::sqrt(hh[4 * (ncv + 1)]);
+      if (!(bn == bn)) return fail(USP_ERR_NAN, "non-finite values in the Lanczos basis");
+      Hm(j + 1, j) = bn;
+      beta_last = bn;
+      if (bn <= 1e-14 * std::abs(Hm(j, j))) {   // invariant subspace: the Ritz pairs are exact
+        m = j + 1;
+        beta_last = 0.0;
+        break;
+      }
+      hipLaunchKernelGGL(k_kscale<C>, dim3(vb), dim3(256), 0, op->st, basis(j + 1), (const C*)w, n,
+                         (const double*)(ks + KS_NRM));
+      LAUNCHCHK("k_kscale");
+    }
+    if (m < nev) return fail(USP_ERR_INVALID, "the start vector spans fewer than nev eigenvectors");
+    // Rayleigh-Ritz: eigenpairs of the Hermitian part of the projected matrix
+    std::vector<zd> Tm((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) Tm[(size_t)i * m + j] = 0.5 * (Hm(i, j) + std::conj(Hm(j, i)));
+    hermitian_jacobi(m, Tm, theta, S);
+    // wanted: the largest theta (A^-1), i.e. the smallest eigenvalues of A
+    order.resize(m);
+    for (int i = 0; i < m; ++i) order[i] = m - 1 - i;
+    // Ritz vectors and their true residuals ||A u - lam u|| / ||lam u||
+    done = true;
+    for (int i = 0; i < nev; ++i) {
+      const int c = order[i];
+      C* u = evecs + (size_t)i * n;
+      if ((rc = combine(&S[c], m, u))) return rc;
+      const double lam = 1.0 / theta[c];
+      evals[i] = lam;
+      cbuf[0] = lam;
+      cbuf[1] = 0.0;
+      HIPCHK(hipMemcpyAsync(coef, cbuf.data(), sizeof(double) * 2, hipMemcpyHostToDevice, op->st));
+      HIPCHK(hipMemsetAsync(w, 0, sizeof(C) * n, op->st));
+      hipLaunchKernelGGL(k_maxpy<C>, dim3(vb), dim3(256), 0, op->st, w, (const C*)u, stride, n, 1,
+                         (const double*)coef, 1.0, (double*)nullptr);   // w = lam u
+      LAUNCHCHK("k_maxpy");
+      if ((rc = norm2(op, (const C*)w, op->scal + 1))) return rc;
+      if ((rc = residual_passes<C>(op, u, (const C*)w, B, nullptr, nullptr))) return rc;
+      double hs[2];
+      HIPCHK(hipMemcpyAsync(hs, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
+      HIPCHK(hipStreamSynchronize(op->st));
+      resid[i] = std::sqrt(hs[0] / hs[1]);
+      if (!(resid[i] == resid[i])) return fail(USP_ERR_NAN, "non-finite Ritz vector");
+      if (!(resid[i] < tol)) done = false;
+    }
+    if (done || cycle == max_restarts || beta_last == 0.0) {
+      done = true;
+      break;
+    }
+    // thick restart: keep kk Ritz vectors and the next Lanczos vector
+    const int kk = std::min(ncv - 1, nev + (ncv - nev) / 2);
+    for (int i = 0; i < kk; ++i)
+      if ((rc = combine(&S[order[i]], m, tmpv(i)))) return rc;
+    for (int i = 0; i < kk; ++i)
+      HIPCHK(hipMemcpyAsync(basis(i), tmpv(i), sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+    HIPCHK(hipMemcpyAsync(basis(kk), basis(ncv), sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+    std::fill(H.begin(), H.end(), zd(0.0));
+    for (int i = 0; i < kk; ++i) {
+      Hm(i, i) = theta[order[i]];
+      Hm(kk, i) = beta_last * S[(size_t)(m - 1) * m + order[i]];
+    }
+    k = kk;
+  }
+  // ascending eigenvalues of A (the order of the loop above already is)
+  if (restarts_out) *restarts_out = cycle;
+  if (inner_out) *inner_out = total_inner;
+  HIPCHK(hipStreamSynchronize(op->st));
+  bool conv = true;
+  for (int i = 0; i < nev; ++i) conv = conv && resid[i] < tol;
+  return conv ? USP_OK : USP_MAXIT;
 }
 
 void cmulh(const double a[2], const double b[2], double out[2]) {
@@ -1011,6 +1314,57 @@ int usp_krylov_workspace_bytes(usp_op op, int method, int restart, size_t* bytes
   return 0;
 }
 
+int usp_hermitian_eig(int n, const double* a, double* w_out, double* z_out) {
+  if (n < 1 || n > 256 || !a || !w_out || !z_out) return fail(USP_ERR_INVALID, "n in [1, 256] and non-NULL arrays");
+  std::vector<zd> A((size_t)n * n);
+  for (size_t i = 0; i < A.size(); ++i) {
+    if (!std::isfinite(a[2 * i]) || !std::isfinite(a[2 * i + 1])) return fail(USP_ERR_NAN, "non-finite matrix entry");
+    A[i] = zd(a[2 * i], a[2 * i + 1]);
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      A[(size_t)i * n + j] = 0.5 * (A[(size_t)i * n + j] + std::conj(A[(size_t)j * n + i]));
+  std::vector<double> w;
+  std::vector<zd> Z;
+  hermitian_jacobi(n, A, w, Z);
+  for (int i = 0; i < n; ++i) w_out[i] = w[i];
+  for (size_t i = 0; i < Z.size(); ++i) {
+    z_out[2 * i] = Z[i].real();
+    z_out[2 * i + 1] = Z[i].imag();
+  }
+  return 0;
+}
+
+int usp_eigs_workspace_bytes(usp_op op, int nev, int ncv, size_t* bytes) {
+  if (!op || !bytes) return fail(USP_ERR_INVALID, "NULL argument");
+  EigWork ew;
+  int rc = eigs_layout(op, nev, ncv, &ew);
+  if (rc) return rc;
+  *bytes = ew.total;
+  return 0;
+}
+
+int usp_eigs(usp_op op, int nev, int ncv, const void* v0_dev, double tol, int max_restarts, double inner_tol,
+             int inner_maxit, void* evecs_dev, double* evals_out, double* resid_out, void* ws_dev, size_t ws_bytes,
+             int* restarts_out, int* inner_iters_out) {
+  if (!op || !v0_dev || !evecs_dev || !evals_out || !resid_out) return fail(USP_ERR_INVALID, "NULL argument");
+  if (!(tol > 0.0) || max_restarts < 0 || !(inner_tol > 0.0) || inner_maxit < 1)
+    return fail(USP_ERR_INVALID, "tol > 0, max_restarts >= 0, inner_tol > 0, inner_maxit >= 1");
+  EigWork ew;
+  int rc = eigs_layout(op, nev, ncv, &ew);
+  if (rc) return rc;
+  if (!ws_dev || ws_bytes < ew.total)
+    return fail(USP_ERR_WORKSPACE, "eigs workspace too small: need " + std::to_string(ew.total) + " bytes");
+  if ((rc = krylov_bind(&ew.kw, ws_dev, ws_bytes))) return rc;
+  if (op->dtype == USP_C64)
+    return eigs_run<float2>(op, nev, ncv, (const float2*)v0_dev, tol, max_restarts, inner_tol, inner_maxit,
+                            (float2*)evecs_dev, evals_out, resid_out, (char*)ws_dev, ew, restarts_out,
+                            inner_iters_out);
+  return eigs_run<double2>(op, nev, ncv, (const double2*)v0_dev, tol, max_restarts, inner_tol, inner_maxit,
+                           (double2*)evecs_dev, evals_out, resid_out, (char*)ws_dev, ew, restarts_out,
+                           inner_iters_out);
+}
+
 int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void* x_dev, int x_is_guess, double tol,
                      int maxit, int check_every, void* ws_dev, size_t ws_bytes, int* iters_out, double* hist_est,
                      int hist_est_cap, double* hist_true, int hist_true_cap, int* n_true_out) {
@@ -1021,7 +1375,13 @@ int usp_solve_krylov(usp_op op, int method, int restart, const void* y_dev, void
   if (rc) return rc;
   if ((rc = krylov_bind(&kw, ws_dev, ws_bytes))) return rc;
   Monitor mon{hist_est, hist_est_cap, hist_true, hist_true_cap};
-  if (method == USP_KRYLOV_BICGSTAB) {
+  if (method == USP_KRYLOV_CG) {
+    rc = op->dtype == USP_C64
+             ? solve_cg<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, tol, maxit, check_every, kw,
+                                iters_out, mon)
+             : solve_cg<double2>(op, (const double2*)y_dev, (double2*)x_dev, x_is_guess, tol, maxit, check_every, kw,
+                                 iters_out, mon);
+  } else if (method == USP_KRYLOV_BICGSTAB) {
     rc = op->dtype == USP_C64
              ? solve_bicgstab<float2>(op, (const float2*)y_dev, (float2*)x_dev, x_is_guess, tol, maxit, check_every,
                                       kw, iters_out, mon)

@@ -1,5 +1,6 @@
-// Kernels of the Krylov drivers (BiCGSTAB, restarted GMRES(m)) on the
-// preconditioned system with the forward problem eliminated (Sec. 2.1):
+// Kernels of the Krylov drivers (BiCGSTAB, restarted GMRES(m), CG for
+// Hermitian positive definite systems) on the preconditioned system with the
+// forward problem eliminated (Sec. 2.1):
 //     P v = B [v - (L + I)^-1 (B v)],      b = B (L + I)^-1 y,
 // so one step of Algorithm 1 is x <- x + alpha (b - P x).
 //
@@ -18,9 +19,11 @@ namespace usp {
 // slots of the device scalar array (doubles, complex values as re, im)
 enum KSlot {
   KS_RHO = 0, KS_RHON = 2, KS_ALPHA = 4, KS_OMEGA = 6, KS_BETA = 8, KS_RV = 10, KS_TS = 12, KS_TT = 14,
-  KS_RR = 15, KS_FLAG = 16, KS_NRM = 17, KS_H = 32
+  KS_RR = 15, KS_FLAG = 16, KS_NRM = 17,
+  KS_CRR = 18, KS_CPQ = 20, KS_CRRN = 22, KS_CALPHA = 24, KS_CBETA = 26,   // CG
+  KS_H = 32, KS_COEF = 512
 };
-enum KScalMode { KSM_INIT = 0, KSM_BETA = 1, KSM_ALPHA = 2, KSM_OMEGA = 3 };
+enum KScalMode { KSM_INIT = 0, KSM_BETA = 1, KSM_ALPHA = 2, KSM_OMEGA = 3, KSM_CG_ALPHA = 4, KSM_CG_BETA = 5 };
 
 __device__ __forceinline__ void zdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {
   const double d = br * br + bi * bi;
@@ -56,6 +59,19 @@ __global__ void k_kscal(double* ks, int mode) {
     } else {
       zdiv(ks[KS_RHO], ks[KS_RHO + 1], dr, di, ks[KS_ALPHA], ks[KS_ALPHA + 1]);
     }
+  } else if (mode == KSM_CG_ALPHA) {  // CG: alpha = |r|^2 / <p, P p>
+    const double dr = ks[KS_CPQ], di = ks[KS_CPQ + 1];
+    if (dr == 0.0 && di == 0.0) {
+      ks[KS_CALPHA] = ks[KS_CALPHA + 1] = 0.0;
+      ks[KS_FLAG] += 1.0;
+    } else {
+      zdiv(ks[KS_CRR], 0.0, dr, di, ks[KS_CALPHA], ks[KS_CALPHA + 1]);
+    }
+  } else if (mode == KSM_CG_BETA) {  // CG: beta = |r_new|^2 / |r|^2
+    const double rr = ks[KS_CRR];
+    ks[KS_CBETA] = rr > 0.0 ? ks[KS_CRRN] / rr : 0.0;
+    ks[KS_CBETA + 1] = 0.0;
+    ks[KS_CRR] = ks[KS_CRRN];
   } else {  // omega = <t, s> / <t, t>
     const double tt = ks[KS_TT];
     if (tt == 0.0) {
@@ -238,6 +254,42 @@ __global__ void __launch_bounds__(256) k_bicg_r(C* __restrict__ x, const C* __re
   }
   block_partial2(dr, di, scratch, rows, rows + pitch);
   block_partial(rr, scratch, rows + 2 * pitch);
+}
+
+// CG: x = x + alpha p;  r = r - alpha q;  |r|^2 partials in row 0
+template <class C>
+__global__ void __launch_bounds__(256) k_cg_x(C* __restrict__ x, C* __restrict__ r, const C* __restrict__ p,
+                                              const C* __restrict__ q, const double* __restrict__ ks, long n,
+                                              double* __restrict__ rows) {
+  __shared__ double scratch[64];
+  const C alpha = kz<C>(ks + KS_CALPHA);
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    x[i] = cadd(x[i], cmul(alpha, p[i]));
+    const C ri = csub(r[i], cmul(alpha, q[i]));
+    r[i] = ri;
+    acc += (double)ri.x * ri.x + (double)ri.y * ri.y;
+  }
+  block_partial(acc, scratch, rows);
+}
+
+// CG: p = r + beta p
+template <class C>
+__global__ void __launch_bounds__(256) k_cg_p(C* __restrict__ p, const C* __restrict__ r,
+                                              const double* __restrict__ ks, long n) {
+  const typename real_of<C>::type beta = (typename real_of<C>::type)ks[KS_CBETA];
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    p[i] = cadd(r[i], cscale(p[i], beta));
+}
+
+// sum of (Im z)^2 partials in row 0 (a test that B is real)
+template <class C>
+__global__ void __launch_bounds__(256) k_imag2(const C* __restrict__ z, long n, double* __restrict__ rows) {
+  __shared__ double scratch[64];
+  double acc = 0.0;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    acc += (double)z[i].y * z[i].y;
+  block_partial(acc, scratch, rows);
 }
 
 // GMRES: partials of <V_i, w> for i < k (rows 2i, 2i + 1; basis vector i at

@@ -274,11 +274,13 @@ def double_ring_well(n=512, box=6.0, depth=10.0, diameter=2.0, width=0.2, gap=0.
     return V, h
 
 
-def harmonic_well(n=40, h=0.45, omega=1.0):
-    """V = omega^2 r^2 / 2 about the grid centre on an n x n grid.  Returns (V, h)."""
+def harmonic_well(n=40, h=0.45, omega=1.0, omega_y=None):
+    """V = (omega^2 x^2 + omega_y^2 y^2) / 2 about the grid centre on an n x n grid
+    (omega_y = omega unless given; x is axis 1).  Returns (V, h)."""
+    wy = omega if omega_y is None else omega_y
     c = (np.arange(n) - n / 2) * h
     yy, xx = np.meshgrid(c, c, indexing="ij")
-    return 0.5 * omega ** 2 * (xx ** 2 + yy ** 2), h
+    return 0.5 * (omega ** 2 * xx ** 2 + wy ** 2 * yy ** 2), h
 
 
 def random_start(shape, seed=0):

@@ -15,7 +15,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["Operator", "FluxOperator", "canonical_flux_host", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
+__all__ = ["Operator", "FluxOperator", "canonical_flux_host", "canonical_schrodinger", "EigResult", "hermitian_eig", "SolveResult", "make_symbol", "smallest_circle", "canonical_helmholtz",
            "canonical_diffusion", "canonical_pantograph", "canonical_fields"]
 
 
@@ -134,6 +134,29 @@ def canonical_diffusion(mu_a, D, omega_over_v, source, spacing, vnorm: float = 0
     S = torch.from_numpy(np.ascontiguousarray(np.asarray(source, dtype=np.complex128))).to(device)
     Bt, yt = canonical_fields(q, S, complex(b[0], b[1]), complex(c[0], c[1]), 1.0, dtype)
     return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
+
+
+def canonical_schrodinger(V, spacing, shift, vnorm: float = 0.95, dtype=torch.complex128,
+                          device="cuda") -> Canonical:
+    """H + shift = -1/2 laplacian + V + shift as the constant-D operator with D = 1/2,
+    mu = V + shift, omega = 0 (Sec. 4, Eq. schrodinger); energies E = c lam - shift."""
+    V = np.asarray(V, dtype=np.float64)
+    return canonical_diffusion(V + shift, 0.5, 0.0, np.zeros(V.shape), spacing, vnorm=vnorm, dtype=dtype,
+                               device=device)
+
+
+@dataclass
+class EigResult:
+    evals: np.ndarray          # ascending eigenvalues of the canonical A
+    evecs: torch.Tensor        # (nev,) + field shape, unit norm
+    resid: np.ndarray          # ||A u - lam u|| / ||lam u||
+    restarts: int
+    inner_iterations: int      # CG iterations over all inner solves
+    status: int
+
+    @property
+    def converged(self):
+        return self.status == L.USP_OK
 
 
 @dataclass
@@ -296,7 +319,7 @@ class Operator:
         y = self._field(y)
         guess = x is not None
         x = self._field(x) if guess else torch.empty_like(y)
-        meth = {"bicgstab": L.USP_KRYLOV_BICGSTAB, "gmres": L.USP_KRYLOV_GMRES}[method]
+        meth = {"bicgstab": L.USP_KRYLOV_BICGSTAB, "gmres": L.USP_KRYLOV_GMRES, "cg": L.USP_KRYLOV_CG}[method]
         nb = ct.c_size_t()
         L.check(L.lib().usp_krylov_workspace_bytes(self.handle, meth, int(restart), ct.byref(nb)))
         ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
@@ -311,6 +334,26 @@ class Operator:
         m = min(nt.value, ntc)
         return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:min(it.value, hc)].copy(),
                            hist_true=ht[:2 * m].reshape(m, 2).copy())
+
+    def eigs(self, nev=5, ncv=32, v0=None, tol=1e-8, max_restarts=50, inner_tol=1e-11, inner_maxit=2000,
+             seed=0) -> EigResult:
+        """usp_eigs: the nev smallest eigenvalues of a Hermitian canonical A and their
+        eigenvectors (shift-invert Lanczos, CG inner solves, thick restart)."""
+        if v0 is None:
+            g = torch.Generator(device="cpu").manual_seed(seed)
+            v0 = torch.randn(self.shape, generator=g, dtype=torch.float64).to(self.dtype).to(self.device)
+        v0 = self._field(v0)
+        nb = ct.c_size_t()
+        L.check(L.lib().usp_eigs_workspace_bytes(self.handle, int(nev), int(ncv), ct.byref(nb)))
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        evecs = torch.empty((nev,) + tuple(self.shape), dtype=self.dtype, device=self.device)
+        ev = np.zeros(nev)
+        rs = np.zeros(nev)
+        nr, ni = ct.c_int(), ct.c_int()
+        rc = L.check(L.lib().usp_eigs(self.handle, int(nev), int(ncv), _ptr(v0), float(tol), int(max_restarts),
+                                      float(inner_tol), int(inner_maxit), _ptr(evecs), _dp(ev), _dp(rs), _ptr(ws),
+                                      nb.value, ct.byref(nr), ct.byref(ni)))
+        return EigResult(evals=ev, evecs=evecs, resid=rs, restarts=nr.value, inner_iterations=ni.value, status=rc)
 
     def apply_precond(self, v, rhs=False):
         """usp_apply_precond: P v, or b = B (L + I)^-1 v with rhs."""
@@ -328,6 +371,17 @@ class Operator:
         L.check(L.lib().usp_residual(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), _dp(rel), _dp(rn),
                                      _dp(yn)))
         return float(rel[0]), float(rn[0]), float(yn[0])
+
+
+def hermitian_eig(a):
+    """usp_hermitian_eig (host): ascending eigenvalues and eigenvector columns of the
+    Hermitian part of a square complex matrix."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    n = a.shape[0]
+    w = np.zeros(n)
+    z = np.zeros((n, n), np.complex128)
+    L.check(L.lib().usp_hermitian_eig(n, _dp(a.view(np.float64)), _dp(w), _dp(z.view(np.float64))))
+    return w, z
 
 
 def canonical_flux_host(mu, D, source, h, vnorm: float = 0.95):

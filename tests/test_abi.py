@@ -154,3 +154,24 @@ def test_host_canonical_flux_matches_oracle():
     Ds[3, 3] = 0.0
     with pytest.raises(_lib.UspError):
         solver.canonical_flux_host(p.mu, Ds, p.source, p.h)
+
+
+def test_host_hermitian_eig_matches_numpy():
+    """The Jacobi eigensolver of the Rayleigh-Ritz step against numpy.linalg.eigh,
+    including repeated eigenvalues (eigenvectors checked through A Z = Z diag(w))."""
+    from paper_2207_14222_amd import solver
+    rng = np.random.default_rng(9)
+    cases = []
+    for n in (1, 2, 5, 40, 64):
+        m = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        cases.append(m + m.conj().T)
+    q, _ = np.linalg.qr(rng.standard_normal((12, 12)) + 1j * rng.standard_normal((12, 12)))
+    d = np.array([1.0, 1.0, 1.0, 2.0, 2.0, -3.0, 5.0, 5.0, 5.0, 5.0, 0.5, 7.0])
+    cases.append(q @ np.diag(d) @ q.conj().T)
+    cases.append(np.diag(rng.standard_normal(9)).astype(complex))   # already diagonal
+    for a in cases:
+        w, z = solver.hermitian_eig(a)
+        scale = max(1.0, float(np.abs(a).max()))
+        assert np.allclose(w, np.linalg.eigvalsh(a), atol=1e-12 * scale)
+        assert np.allclose(z.conj().T @ z, np.eye(len(w)), atol=1e-12)
+        assert np.allclose(a @ z, z * w[None, :], atol=1e-11 * scale)
