@@ -18,7 +18,8 @@ on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
 the other workloads under "modes": BiCGSTAB and GMRES(m) on the same
 preconditioned operator, the pantograph in direct and antisymmetrised
 form, diffusion (plain vs refined), flux-form tensor diffusion on the
-256 x 256 ring, 96 batched
+256 x 256 ring, the five lowest eigenmodes of a double-ring well (512 x 512,
+Lanczos with CG inner solves), 96 batched
 2-D problems in one graph-captured schedule, and the learned initial guess
 on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
 protocol is 2000 / 200 media).
@@ -297,6 +298,40 @@ def bench_flux(args, log):
     return out
 
 
+def bench_eigen(args, log):
+    """Five lowest modes of the double-ring well (Sec. 4, Eq. schrodinger) on a
+    512 x 512 grid, complex128: H + 5 in canonical form, shift-invert Lanczos
+    (24 basis vectors, thick restart) with CG inner solves on the preconditioned
+    system to 1e-11, Ritz residual 1e-8.  Bytes per CG iteration: P p (k_kfirst
+    reads p, B, writes t; the symbol pass reads and writes t; k_klast reads t,
+    p, B, writes q: 9 arrays) and the vector updates (x, r from x, r, p, q: 6;
+    p from r, p: 3), 18 arrays of N complex128 values."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    V, h = media.double_ring_well(n=512)
+    shift = 5.0
+    can = solver.canonical_schrodinger(V, (h, h), shift, dtype=torch.complex128)
+    op = solver.Operator(can.symbol, can.B)
+    kw = dict(nev=5, ncv=24, tol=1e-8, inner_tol=1e-11, max_restarts=30)
+    op.eigs(**kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.eigs(**kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = V.size
+    cg_bytes = 18 * n * 16
+    energies = (np.real(can.c) * r.evals - shift).tolist()
+    out = {"time_ms": round(dt * 1e3, 2), "status": "converged" if r.converged else "maxit",
+           "restarts": r.restarts, "cg_iterations": r.inner_iterations,
+           "us_per_cg_iteration": round(dt * 1e6 / max(1, r.inner_iterations), 2),
+           "model_GB/s_per_cg_iter": round(cg_bytes * r.inner_iterations / dt / 1e9, 1),
+           "energies": [round(e, 8) for e in energies], "max_resid": float(np.max(r.resid))}
+    op.close()
+    log(f"eigenmodes: {out}")
+    return out
+
+
 def bench_learned(args, log):
     """Learned initial guess on 128^3 random-sphere media (shared canonical scaling):
     training data from solves of the method (seeds 0..), Adam training of the
@@ -361,6 +396,7 @@ def main():
     ap.add_argument("--batch-n", type=int, default=96)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess workload")
     ap.add_argument("--no-flux", action="store_true", help="skip the flux-form tensor diffusion workload")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the eigenmode workload")
     ap.add_argument("--learned-train", type=int, default=600, help="training media (the full protocol uses 2000)")
     ap.add_argument("--learned-test", type=int, default=30, help="held-out media (the full protocol uses 200)")
     ap.add_argument("--learned-epochs", type=int, default=4)
@@ -505,6 +541,11 @@ def main():
     if not args.no_flux:
         log("flux-form tensor diffusion (256 x 256 ring)")
         extra["flux_ring256"] = bench_flux(args, log)
+        torch.cuda.empty_cache()
+
+    if not args.no_eigen:
+        log("eigenmodes of the double-ring well (512 x 512)")
+        extra["eigen_ring512"] = bench_eigen(args, log)
         torch.cuda.empty_cache()
 
     if not args.no_batch:
