@@ -144,7 +144,10 @@ int usp_prepare_operator(const usp_symbol* L, int dtype, int flags, const void* 
  *   alpha          step size (> 0; (0, 1] is always contractive, Corollary 1).
  *   check_every    true residual evaluated (in FP64) every check_every
  *                  iterations; in refined mode this is the refinement interval
- *                  k (residual recomputed and accumulated in FP64 every k steps).
+ *                  k (residual recomputed and accumulated in FP64 every k steps),
+ *                  except that a cycle is shortened to the number of steps the
+ *                  current rate of ||Delta|| (last 10 iterations) predicts for
+ *                  reaching tol when that is under half the cycle.
  *   iters_out      iterations performed.
  *   hist_pre       host array, may be NULL: ||Delta_i||^2 for i < hist_pre_cap.
  *   hist_true      host array, may be NULL: pairs (iteration, ||y - A x||/||y||)

@@ -263,9 +263,13 @@ struct Monitor {
   double d_first = -1.0, d_prev = -1.0;
   int grow = 0;
   bool diverged = false, nan = false;
+  double tail[16];   // the latest ||Delta||^2 values (ring)
+  int ntail = 0;
 
   void delta(int it, double dd) {
     if (hist_pre && it < hist_pre_cap) hist_pre[it] = dd;
+    tail[ntail % 16] = dd;
+    ++ntail;
     if (!(dd == dd)) nan = true;
     if (d_first < 0) d_first = dd;
     grow = (d_prev >= 0 && dd > d_prev) ? grow + 1 : 0;
@@ -402,8 +406,23 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
     if (mon.diverged) { status = USP_DIVERGED; break; }
     if (stag) { status = USP_STAGNATED; break; }
     if (it >= maxit) break;
-    // inner complex64 iterations on A d = r from d = 0
-    const int m = std::min(k, maxit - it);
+    // inner complex64 iterations on A d = r from d = 0: k of them, or fewer when
+    // the current convergence rate predicts the crossing of tol sooner (the
+    // iteration keeps no state besides x, so x + d_m is the m-th iterate from x
+    // and the residual keeps decaying at the rate of ||Delta||)
+    int m = std::min(k, maxit - it);
+    if (mon.ntail >= 11) {
+      // current rate per iteration from the last 10 ||Delta|| values (it
+      // slows as the slowest modes take over, so the latest is the best guide)
+      const double a = mon.tail[(mon.ntail - 1) % 16], b = mon.tail[(mon.ntail - 11) % 16];
+      if (a > 0.0 && a < b) {
+        const double lrate = 0.05 * std::log(a / b);   // log of the per-iteration factor of ||Delta||
+        const double need = std::log(tol / rho) / lrate;
+        // trusted only within half a cycle: further out the slowing rate makes
+        // it stop short, and a short cycle costs a whole FP64 check
+        if (need < 0.5 * m) m = std::max(1, (int)std::ceil(1.05 * need) + 1);
+      }
+    }
     HIPCHK(hipMemsetAsync(op->d32, 0, sizeof(float2) * op->d.N, op->st));
     if ((rc = first_pass<float2>(op, op->d32, op->r32, op->B32, 0))) return rc;
     for (int j = 0; j < m; ++j)
