@@ -121,7 +121,10 @@ k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
   constexpr int LDSN = F64 ? 1024 * 5 : 1024 * 9;
   __shared__ C lds[LDSN];
   __shared__ C tws[1024];
-  const GTask tk = tasks[blockIdx.x];
+  // consecutive column tiles (which share cache lines when a tile row is
+  // narrower than a line) on one XCD: blocks are dealt to the 8 XCDs in turn
+  const int nb = gridDim.x, nb8 = nb - nb % 8, bb = blockIdx.x;
+  const GTask tk = tasks[bb < nb8 ? (bb % 8) * (nb8 / 8) + bb / 8 : bb];
   if (st[tk.p].done) return;
   const BatchProblem P = probs[tk.p];
   SymArgs sym;
