@@ -563,24 +563,15 @@ int ksum(usp_op op, const KWork& kw, int row0, int nrows, int ncols, double* out
   return 0;
 }
 
-// w = P v (rhs = false) or w = b from v = y (rhs = true), with fused dot partials
+// the strided passes of P v and its last pass: t (already transformed along
+// n2) -> w = B (v - u) or w = B u (rhs), with fused dot partials
 template <class C>
-int kapply(usp_op op, const C* v, C* w, bool rhs, const C* q, int dots, const KWork& kw) {
+int kapply_tail(usp_op op, const C* v, C* w, bool rhs, const C* q, int dots, const KWork& kw) {
   const Dims& D = op->d;
   const int nlines = D.n0 * D.n1;
   C* t = (C*)op->t;
   const C* B = (const C*)op->B;
   int rc;
-  bool ok = with_n(D.n2, [&](auto NC) {
-    constexpr int N = decltype(NC)::value;
-    constexpr int TPB = x_threads<C>();
-    constexpr int LPB = TPB / (N / PassPlan<N>::E);
-    const int blocks = (nlines + LPB - 1) / LPB;
-    hipLaunchKernelGGL((k_kfirst<C, N>), dim3(blocks), dim3(TPB), 0, op->st, t, v, rhs ? nullptr : B, tw_for<C>(op, N),
-                       nlines);
-  });
-  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
-  LAUNCHCHK("k_kfirst");
   const SymArgs sa = sym_args(op, true);
   const int wm = sizeof(C) == 8 ? op->plan.w_mid : 0, wsy = sizeof(C) == 8 ? op->plan.w_sym : 0;
   if (D.ndim == 3 && (rc = launch_s<C, S_FWD>(op, t, 1, sa, wm))) return rc;
@@ -600,6 +591,26 @@ int kapply(usp_op op, const C* v, C* w, bool rhs, const C* q, int dots, const KW
   });
   LAUNCHCHK("k_klast");
   return 0;
+}
+
+// w = P v (rhs = false) or w = b from v = y (rhs = true), with fused dot partials
+template <class C>
+int kapply(usp_op op, const C* v, C* w, bool rhs, const C* q, int dots, const KWork& kw) {
+  const Dims& D = op->d;
+  const int nlines = D.n0 * D.n1;
+  C* t = (C*)op->t;
+  const C* B = (const C*)op->B;
+  bool ok = with_n(D.n2, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int TPB = x_threads<C>();
+    constexpr int LPB = TPB / (N / PassPlan<N>::E);
+    const int blocks = (nlines + LPB - 1) / LPB;
+    hipLaunchKernelGGL((k_kfirst<C, N>), dim3(blocks), dim3(TPB), 0, op->st, t, v, rhs ? nullptr : B, tw_for<C>(op, N),
+                       nlines);
+  });
+  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
+  LAUNCHCHK("k_kfirst");
+  return kapply_tail<C>(op, v, w, rhs, q, dots, kw);
 }
 
 // true residual ||y - A x||^2 / ||y||^2 (FP64 passes) -> host
@@ -674,45 +685,66 @@ int solve_bicgstab(usp_op op, const C* y, C* x, int x_is_guess, double tol, int 
 }
 
 // Conjugate gradients on P x = b for a Hermitian canonical operator (A, L, V
-// Hermitian; P is then Hermitian, and positive definite when A is).  Scalars
-// stay on the device; the host synchronises at true-residual checks only.
+// Hermitian; P is then Hermitian, and positive definite when A is).  An
+// iteration is four launches: k_cg_first (beta from the summed |r|^2
+// partials, p = r + beta p, B p and its FFT along n2), the strided passes,
+// k_klast (q = P p with the <p, q> partials) and k_cg_update (alpha from the
+// summed partials, x and r, |r|^2 partials).  Every block sums the partial
+// rows it needs in the same fixed order, so no scalar kernel or host round
+// trip sits between them; |r|^2 alternates between two rows (2 and 3).  The
+// host synchronises at true-residual checks only.
 template <class C>
 int solve_cg(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit, int check_every, const KWork& kw,
              int* iters_out, Monitor& mon) {
   const long n = op->d.N;
+  const Dims& D = op->d;
+  const int nlines = D.n0 * D.n1;
   C *r = kw.vec<C>(0), *p = kw.vec<C>(1), *q = kw.vec<C>(2);
   double* ks = kw.ks;
-  const int vb = vec_blocks(n);
+  // grid of the vector kernels: every block of the next pass sums their
+  // partial row, so small problems use fewer (fuller) blocks
+  const int vb = std::min(vec_blocks(n), (int)std::max<long>(256, n / 4096));
   const int xb = x_blocks<C>(op);
+  double* rrow[2] = {kw.rows + 2 * kw.pitch, kw.rows + 3 * kw.pitch};
   int rc;
   if ((rc = norm2(op, y, op->scal + 1))) return rc;
   HIPCHK(hipMemsetAsync(ks, 0, sizeof(double) * 32, op->st));
   if ((rc = kapply<C>(op, y, r, true, nullptr, 0, kw))) return rc;   // r = b
   if (x_is_guess) {
     if ((rc = kapply<C>(op, x, q, false, nullptr, 0, kw))) return rc;
-    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, (const C*)q, n, kw.rows);
-    LAUNCHCHK("k_ksub");                                              // p = b - P x
-    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_CRR))) return rc;
+    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, (const C*)q, n, rrow[0]);
+    LAUNCHCHK("k_ksub");                                              // p = b - P x, |r_0|^2 partials
     HIPCHK(hipMemcpyAsync(r, p, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
   } else {
     HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * n, op->st));
-    if ((rc = norm2(op, (const C*)r, ks + KS_CRR))) return rc;
-    HIPCHK(hipMemcpyAsync(p, r, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
+    hipLaunchKernelGGL(k_knorm2<C>, dim3(vb), dim3(256), 0, op->st, (const C*)r, n, rrow[0]);
+    LAUNCHCHK("k_knorm2");
   }
+  HIPCHK(hipMemsetAsync(p, 0, sizeof(C) * n, op->st));
   int it = 0, status = USP_MAXIT;
   while (it < maxit) {
-    if ((rc = kapply<C>(op, p, q, false, p, 1, kw))) return rc;           // q = P p, <p, q>
-    if ((rc = ksum(op, kw, 0, 2, xb, ks + KS_CPQ))) return rc;
-    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_CG_ALPHA);
-    hipLaunchKernelGGL(k_cg_x<C>, dim3(vb), dim3(256), 0, op->st, x, r, (const C*)p, (const C*)q, ks, n, kw.rows);
-    if ((rc = ksum(op, kw, 0, 1, vb, ks + KS_CRRN))) return rc;
-    hipLaunchKernelGGL(k_kscal, dim3(1), dim3(64), 0, op->st, ks, (int)KSM_CG_BETA);
-    hipLaunchKernelGGL(k_cg_p<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, ks, n);
+    const int cur = it & 1;
+    bool ok = with_n(D.n2, [&](auto NC) {
+      constexpr int N = decltype(NC)::value;
+      constexpr int TPB = x_threads<C>();
+      constexpr int LPB = TPB / (N / PassPlan<N>::E);
+      const int blocks = (nlines + LPB - 1) / LPB;
+      hipLaunchKernelGGL((k_cg_first<C, N>), dim3(blocks), dim3(TPB), 0, op->st, (C*)op->t, p, (const C*)r,
+                         (const C*)op->B, tw_for<C>(op, N), nlines, (const double*)rrow[cur],
+                         it > 0 ? (const double*)rrow[cur ^ 1] : (const double*)nullptr, vb);
+    });
+    if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
+    LAUNCHCHK("k_cg_first");
+    if ((rc = kapply_tail<C>(op, p, q, false, p, 1, kw))) return rc;   // q = P p, <p, q> in rows 0, 1
+    hipLaunchKernelGGL(k_cg_update<C>, dim3(vb), dim3(256), 0, op->st, x, r, (const C*)p, (const C*)q, n,
+                       (const double*)rrow[cur], vb, (const double*)kw.rows, (const double*)(kw.rows + kw.pitch), xb,
+                       rrow[cur ^ 1], ks);
     LAUNCHCHK("cg iteration");
     ++it;
     if (it % check_every == 0 || it == maxit) {
       double rho, hk[2];
       if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
+      if ((rc = ksum(op, kw, 2 + (it & 1), 1, vb, ks + KS_CRR))) return rc;   // |r_it|^2
       HIPCHK(hipMemcpyAsync(hk, ks + KS_FLAG, sizeof(double), hipMemcpyDeviceToHost, op->st));
       HIPCHK(hipMemcpyAsync(hk + 1, ks + KS_CRR, sizeof(double), hipMemcpyDeviceToHost, op->st));
       HIPCHK(hipStreamSynchronize(op->st));

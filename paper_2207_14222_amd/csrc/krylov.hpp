@@ -20,10 +20,10 @@ namespace usp {
 enum KSlot {
   KS_RHO = 0, KS_RHON = 2, KS_ALPHA = 4, KS_OMEGA = 6, KS_BETA = 8, KS_RV = 10, KS_TS = 12, KS_TT = 14,
   KS_RR = 15, KS_FLAG = 16, KS_NRM = 17,
-  KS_CRR = 18, KS_CPQ = 20, KS_CRRN = 22, KS_CALPHA = 24, KS_CBETA = 26,   // CG
+  KS_CRR = 18,   // CG: |r|^2 at a check
   KS_H = 32, KS_COEF = 512
 };
-enum KScalMode { KSM_INIT = 0, KSM_BETA = 1, KSM_ALPHA = 2, KSM_OMEGA = 3, KSM_CG_ALPHA = 4, KSM_CG_BETA = 5 };
+enum KScalMode { KSM_INIT = 0, KSM_BETA = 1, KSM_ALPHA = 2, KSM_OMEGA = 3 };
 
 __device__ __forceinline__ void zdiv(double ar, double ai, double br, double bi, double& cr, double& ci) {
   const double d = br * br + bi * bi;
@@ -59,19 +59,6 @@ __global__ void k_kscal(double* ks, int mode) {
     } else {
       zdiv(ks[KS_RHO], ks[KS_RHO + 1], dr, di, ks[KS_ALPHA], ks[KS_ALPHA + 1]);
     }
-  } else if (mode == KSM_CG_ALPHA) {  // CG: alpha = |r|^2 / <p, P p>
-    const double dr = ks[KS_CPQ], di = ks[KS_CPQ + 1];
-    if (dr == 0.0 && di == 0.0) {
-      ks[KS_CALPHA] = ks[KS_CALPHA + 1] = 0.0;
-      ks[KS_FLAG] += 1.0;
-    } else {
-      zdiv(ks[KS_CRR], 0.0, dr, di, ks[KS_CALPHA], ks[KS_CALPHA + 1]);
-    }
-  } else if (mode == KSM_CG_BETA) {  // CG: beta = |r_new|^2 / |r|^2
-    const double rr = ks[KS_CRR];
-    ks[KS_CBETA] = rr > 0.0 ? ks[KS_CRRN] / rr : 0.0;
-    ks[KS_CBETA + 1] = 0.0;
-    ks[KS_CRR] = ks[KS_CRRN];
   } else {  // omega = <t, s> / <t, t>
     const double tt = ks[KS_TT];
     if (tt == 0.0) {
@@ -256,13 +243,85 @@ __global__ void __launch_bounds__(256) k_bicg_r(C* __restrict__ x, const C* __re
   block_partial(rr, scratch, rows + 2 * pitch);
 }
 
-// CG: x = x + alpha p;  r = r - alpha q;  |r|^2 partials in row 0
-template <class C>
-__global__ void __launch_bounds__(256) k_cg_x(C* __restrict__ x, C* __restrict__ r, const C* __restrict__ p,
-                                              const C* __restrict__ q, const double* __restrict__ ks, long n,
-                                              double* __restrict__ rows) {
+// ordered sum of n partials, the same value in every thread of every block
+// that calls it on the same row (fixed strides, fixed reduction tree)
+__device__ __forceinline__ double row_total(const double* __restrict__ row, int n, double* scratch) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += row[i];
+  return block_sum(acc, scratch);
+}
+
+// Fused CG step, first pass of P p: beta = |r_i|^2 / |r_{i-1}|^2 from the two
+// alternating |r|^2 partial rows (rr_cur, rr_prev; beta = 0 when rr_prev is
+// NULL), p = r + beta p, then t = FFT along n2 of B p.
+template <class C, int N>
+__global__ void __launch_bounds__(x_threads<C>())
+k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const C* __restrict__ B,
+           const C* __restrict__ tw, int nlines, const double* __restrict__ rr_cur, const double* __restrict__ rr_prev,
+           int nrr) {
+  using PP = PassPlan<N>;
+  using Rr = typename real_of<C>::type;
+  constexpr int E = PP::E, T = N / E;
+  constexpr int LPB = (x_threads<C>() / T) > 0 ? (x_threads<C>() / T) : 1;
+  constexpr int TH = LPB * T;
+  __shared__ C lds[LPB * LdsRow<C>::padded(N)];
+  __shared__ C tws[N];
   __shared__ double scratch[64];
-  const C alpha = kz<C>(ks + KS_CALPHA);
+  double beta = 0.0;
+  if (rr_prev) {
+    const double a = row_total(rr_cur, nrr, scratch), b = row_total(rr_prev, nrr, scratch);
+    beta = b > 0.0 ? a / b : 0.0;
+  }
+  load_twiddles<C, N>(tws, tw);
+  const int tid = threadIdx.x;
+  if (tid >= TH) {
+    idle_fft_syncs<N, typename PP::P>();
+    return;
+  }
+  const int tt = tid % T, li = tid / T;
+  const long line = (long)blockIdx.x * LPB + li;
+  const bool active = line < nlines;
+  const long base = line * N;
+  LdsRow<C> row{lds + li * LdsRow<C>::padded(N)};
+  C a[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const long q = base + tt + T * e;
+    C val = mk<C>(0.0, 0.0);
+    if (active) {
+      const C pn = cadd(r[q], cscale(p[q], (Rr)beta));
+      p[q] = pn;
+      val = cmul(B[q], pn);
+    }
+    a[e] = val;
+  }
+  FftRun<C, N, E, -1, 1, typename PP::P>::run(a, tt, row, tws, BlockSync{});
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) t[base + tt + T * e] = a[e];
+  }
+}
+
+// Fused CG step, update: alpha = |r_i|^2 / <p, P p> from the partial rows
+// (rr_cur: nrr partials; pq_re, pq_im: npq partials each), x += alpha p,
+// r -= alpha q, and the partials of |r_{i+1}|^2 into rr_next.  A zero <p, P p>
+// (breakdown) gives alpha = 0 and raises ks[KS_FLAG].
+template <class C>
+__global__ void __launch_bounds__(256) k_cg_update(C* __restrict__ x, C* __restrict__ r, const C* __restrict__ p,
+                                                   const C* __restrict__ q, long n, const double* __restrict__ rr_cur,
+                                                   int nrr, const double* __restrict__ pq_re,
+                                                   const double* __restrict__ pq_im, int npq,
+                                                   double* __restrict__ rr_next, double* __restrict__ ks) {
+  __shared__ double scratch[64];
+  const double rr = row_total(rr_cur, nrr, scratch);
+  const double dr = row_total(pq_re, npq, scratch), di = row_total(pq_im, npq, scratch);
+  double ar = 0.0, ai = 0.0;
+  if (dr == 0.0 && di == 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) ks[KS_FLAG] += 1.0;
+  } else {
+    zdiv(rr, 0.0, dr, di, ar, ai);
+  }
+  const C alpha = mk<C>(ar, ai);
   double acc = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     x[i] = cadd(x[i], cmul(alpha, p[i]));
@@ -270,16 +329,17 @@ __global__ void __launch_bounds__(256) k_cg_x(C* __restrict__ x, C* __restrict__
     r[i] = ri;
     acc += (double)ri.x * ri.x + (double)ri.y * ri.y;
   }
-  block_partial(acc, scratch, rows);
+  block_partial(acc, scratch, rr_next);
 }
 
-// CG: p = r + beta p
+// |z|^2 partials in row 0 (grid-stride)
 template <class C>
-__global__ void __launch_bounds__(256) k_cg_p(C* __restrict__ p, const C* __restrict__ r,
-                                              const double* __restrict__ ks, long n) {
-  const typename real_of<C>::type beta = (typename real_of<C>::type)ks[KS_CBETA];
+__global__ void __launch_bounds__(256) k_knorm2(const C* __restrict__ z, long n, double* __restrict__ rows) {
+  __shared__ double scratch[64];
+  double acc = 0.0;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-    p[i] = cadd(r[i], cscale(p[i], beta));
+    acc += (double)z[i].x * z[i].x + (double)z[i].y * z[i].y;
+  block_partial(acc, scratch, rows);
 }
 
 // sum of (Im z)^2 partials in row 0 (a test that B is real)
