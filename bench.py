@@ -308,10 +308,10 @@ def bench_eigen(args, log):
     """Five lowest modes of the double-ring well (Sec. 4, Eq. schrodinger) on a
     512 x 512 grid, complex128: H + 5 in canonical form, shift-invert Lanczos
     (24 basis vectors, thick restart) with CG inner solves on the preconditioned
-    system to 1e-11, Ritz residual 1e-8.  Bytes per CG iteration: P p (k_kfirst
-    reads p, B, writes t; the symbol pass reads and writes t; k_klast reads t,
-    p, B, writes q: 9 arrays) and the vector updates (x, r from x, r, p, q: 6;
-    p from r, p: 3), 18 arrays of N complex128 values."""
+    system to 1e-11, Ritz residual 1e-8.  Bytes per CG iteration: k_cg_first reads
+    r, p, B and writes p, t (5 arrays), the symbol pass reads and writes t (2),
+    k_klast reads t, p, B and writes q (4), k_cg_update reads x, r, p, q and
+    writes x, r (6): 17 arrays of N complex128 values."""
     import torch
     from paper_2207_14222_amd import media, solver
     V, h = media.double_ring_well(n=512)
@@ -326,7 +326,7 @@ def bench_eigen(args, log):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n = V.size
-    cg_bytes = 18 * n * 16
+    cg_bytes = 17 * n * 16
     energies = (np.real(can.c) * r.evals - shift).tolist()
     out = {"time_ms": round(dt * 1e3, 2), "status": "converged" if r.converged else "maxit",
            "restarts": r.restarts, "cg_iterations": r.inner_iterations,
