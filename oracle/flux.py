@@ -1,28 +1,31 @@
 """Diffusion in flux form with a tensor diffusion coefficient (Sec. 3.2, Eq.
-diffusion-equation-matrix-form), steady state, on a 2-D periodic grid.
+diffusion-equation-matrix-form), steady state, on a periodic 2-D or 3-D grid.
 
 TEST INFRASTRUCTURE (FP64 oracle) -- see ``oracle/__init__.py``.
 
-Fick's two laws, div J + mu u = S and D^-1 J + grad u = 0, on x~ = [u; Jx; Jy]
-(x the contiguous axis 1, y axis 0):
+Fick's two laws, div J + mu u = S and D^-1 J + grad u = 0, on
+x~ = [u; J_1; ...; J_d] (d = 2 or 3).  Flux component k pairs with grid axis
+d - k: J_1 = J_x with the contiguous (last) axis, J_2 = J_y with the one
+before, J_3 = J_z with axis 0 in 3-D.  With d_k the spectral derivative along
+that axis (symbol i p, Nyquist mode zero so that d is skew-Hermitian),
 
-    A~ = [[mu, d_x, d_y], [d_x, Di_xx, Di_xy], [d_y, Di_yx, Di_yy]],   y~ = [S; 0; 0],
+    A~ = [[mu, d_1 .. d_d], [d_1 .. d_d (column), D^-1]],   y~ = [S; 0 .. 0],
 
-with Di = D^-1 per voxel and d the spectral derivative (symbol i p, Nyquist
-mode zero so that d is skew-Hermitian).  Splitting: L~ keeps the derivatives
-and the biases mubar (smallest circle of {mu}) and Dibar (smallest circle of
-each element of {Di} separately); V~ = blockdiag(mu - mubar, Di - Dibar).
+D = [[D_xx, D_xy, ..], ..] in the (x, y[, z]) order of the flux components and
+D^-1 its per-voxel inverse.  Splitting: L~ keeps the derivatives and the
+biases mubar (smallest circle of {mu}) and Dibar (smallest circle of each
+element of {D^-1} separately); V~ = blockdiag(mu - mubar, D^-1 - Dibar).
 Scaling (reading of the equilibration step): the radii of the circles form
-dV = [[R_mu, 0, 0], [0, R_xx, R_xy], [0, R_yx, R_yy]]; a diagonal s > 0 is
-found by symmetric infinity-norm equilibration (s_i <- s_i / sqrt(max_j s_i
-dV_ij s_j), 50 sweeps; zero rows keep s_i = 1), then c = max over voxels of
-||S V~ S||_2 / 0.95 (S = diag(s)).  The canonical system is
+dV = blockdiag(R_mu, [R_ab]); a diagonal s > 0 is found by symmetric
+infinity-norm equilibration (s_i <- s_i / sqrt(max_j s_i dV_ij s_j), 50
+sweeps; zero rows keep s_i = 1), then c = max over voxels of ||S V~ S||_2 /
+0.95 (S = diag(s)).  The canonical system is
 
     A = S A~ S / c,   x = sqrt(c) S^-1 [u; J],   y = S y~ / sqrt(c),
 
 so ||V|| = 0.95 and [u; J] = S x / sqrt(c).  L's symbol is S L~(p) S / c, a
-3 x 3 block per Fourier mode, and (L + I)^-1 is its per-mode inverse.
-Fields are arrays of shape (3, n0, n1).
+(1 + d) x (1 + d) block per Fourier mode, and (L + I)^-1 is its per-mode
+inverse.  Fields are arrays of shape (1 + d,) + grid.
 """
 from __future__ import annotations
 
@@ -56,23 +59,29 @@ def equilibrate(dV, sweeps=50):
 
 @dataclass
 class FluxCanonical:
-    shape: tuple         # (n0, n1)
+    shape: tuple         # grid shape (n0, n1[, n2])
     h: float
-    s: np.ndarray        # (3,) equilibration
+    s: np.ndarray        # (1 + d,) equilibration
     c: float             # overall scale
     mubar: complex
-    Dibar: np.ndarray    # (2, 2) complex
-    Buu: np.ndarray      # (n0, n1) complex: 1 - s0^2 (mu - mubar)/c
-    B2: np.ndarray       # (n0, n1, 2, 2): I - S2 (Di - Dibar) S2 / c
-    y: np.ndarray        # (3, n0, n1)
+    Dibar: np.ndarray    # (d, d) complex
+    Buu: np.ndarray      # grid: 1 - s0^2 (mu - mubar)/c
+    B2: np.ndarray       # grid + (d, d): I - S' (Di - Dibar) S' / c
+    y: np.ndarray        # (1 + d,) + grid
     radii: np.ndarray    # dV
+
+    @property
+    def ndim(self):
+        return len(self.shape)
 
 
 def canonical_flux(mu, D, source, h, vnorm=VNORM) -> FluxCanonical:
-    """mu (n0, n1), D (n0, n1, 2, 2) (the tensor [[Dxx, Dxy], [Dyx, Dyy]]), source (n0, n1)."""
+    """mu (grid), D (grid + (d, d)) in the (x, y[, z]) order of the flux components, source (grid)."""
     mu = np.asarray(mu, dtype=np.complex128)
     D = np.asarray(D, dtype=np.complex128)
+    d = mu.ndim
     Di = np.linalg.inv(D)
+
     def circle(vals):   # a constant set is its own centre, radius 0
         vals = vals.ravel()
         if np.all(vals == vals[0]):
@@ -80,12 +89,12 @@ def canonical_flux(mu, D, source, h, vnorm=VNORM) -> FluxCanonical:
         return smallest_circle(vals)
 
     mubar, Rmu = circle(mu)
-    Dibar = np.zeros((2, 2), dtype=np.complex128)
-    R2 = np.zeros((2, 2))
-    for a in range(2):
-        for b in range(2):
+    Dibar = np.zeros((d, d), dtype=np.complex128)
+    R2 = np.zeros((d, d))
+    for a in range(d):
+        for b in range(d):
             Dibar[a, b], R2[a, b] = circle(Di[..., a, b])
-    dV = np.zeros((3, 3))
+    dV = np.zeros((1 + d, 1 + d))
     dV[0, 0] = Rmu
     dV[1:, 1:] = R2
     s = equilibrate(dV)
@@ -97,8 +106,8 @@ def canonical_flux(mu, D, source, h, vnorm=VNORM) -> FluxCanonical:
     if not c > 0.0:
         c = 1.0
     Buu = 1.0 - Vu / c
-    B2 = np.eye(2) - V2 / c
-    y = np.zeros((3,) + mu.shape, dtype=np.complex128)
+    B2 = np.eye(d) - V2 / c
+    y = np.zeros((1 + d,) + mu.shape, dtype=np.complex128)
     y[0] = s[0] * np.asarray(source, dtype=np.complex128) / np.sqrt(c)
     return FluxCanonical(shape=mu.shape, h=float(h), s=s, c=c, mubar=mubar, Dibar=Dibar, Buu=Buu, B2=B2, y=y,
                          radii=dV)
@@ -109,25 +118,29 @@ class FluxOperator:
 
     def __init__(self, cp: FluxCanonical):
         self.cp = cp
-        n0, n1 = cp.shape
-        self.shape = (3, n0, n1)
-        p0 = _dspec(n0, cp.h)[:, None] * np.ones((1, n1))
-        p1 = np.ones((n0, 1)) * _dspec(n1, cp.h)[None, :]
+        d = len(cp.shape)
+        self.d = d
+        self.shape = (1 + d,) + tuple(cp.shape)
         s, c = cp.s, cp.c
-        Lt = np.zeros((n0, n1, 3, 3), dtype=np.complex128)
+        Lt = np.zeros(tuple(cp.shape) + (1 + d, 1 + d), dtype=np.complex128)
         Lt[..., 0, 0] = cp.mubar
-        Lt[..., 0, 1] = 1j * p1
-        Lt[..., 0, 2] = 1j * p0
-        Lt[..., 1, 0] = 1j * p1
-        Lt[..., 2, 0] = 1j * p0
+        for k in range(1, d + 1):
+            ax = d - k                               # flux component k pairs with axis d - k
+            pk = _dspec(cp.shape[ax], cp.h)
+            shp = [1] * d
+            shp[ax] = cp.shape[ax]
+            pk = pk.reshape(shp)
+            Lt[..., 0, k] = 1j * pk
+            Lt[..., k, 0] = 1j * pk
         Lt[..., 1:, 1:] = cp.Dibar
         self.lsym = (s[:, None] * s[None, :]) * Lt / c          # S L~(p) S / c per mode
-        self.lsym_inv = np.linalg.inv(self.lsym + np.eye(3))
+        self.lsym_inv = np.linalg.inv(self.lsym + np.eye(1 + d))
 
     def _modes(self, x, M):
-        xh = np.fft.fft2(x, axes=(1, 2))
+        axes = tuple(range(1, self.d + 1))
+        xh = np.fft.fftn(x, axes=axes)
         yh = np.einsum("...ij,j...->i...", M, xh)
-        return np.fft.ifft2(yh, axes=(1, 2))
+        return np.fft.ifftn(yh, axes=axes)
 
     def apply_L(self, x):
         return self._modes(x, self.lsym)
@@ -139,9 +152,8 @@ class FluxOperator:
         cp = self.cp
         out = np.empty_like(x)
         out[0] = (1.0 - cp.Buu) * x[0]
-        V2 = np.eye(2) - cp.B2
-        out[1] = V2[..., 0, 0] * x[1] + V2[..., 0, 1] * x[2]
-        out[2] = V2[..., 1, 0] * x[1] + V2[..., 1, 1] * x[2]
+        V2 = np.eye(self.d) - cp.B2
+        out[1:] = np.einsum("...ab,b...->a...", V2, x[1:])
         return out
 
     def apply_B(self, x):
@@ -165,4 +177,4 @@ class FluxOperator:
 
     def physical(self, x):
         """[u; J] = S x / sqrt(c)."""
-        return self.cp.s[:, None, None] * x / np.sqrt(self.cp.c)
+        return self.cp.s.reshape((-1,) + (1,) * self.d) * x / np.sqrt(self.cp.c)

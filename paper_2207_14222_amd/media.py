@@ -289,6 +289,26 @@ def random_start(shape, seed=0):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
+def diffusion_tensor_random3(shape=(8, 16, 32), seed=11, h=0.3, d_lo=0.5, mu_lo=0.05, mu_hi=1.0, smooth=2.0):
+    """Random anisotropic 3-D medium: per voxel D = G G^T / 3 + d_lo I (symmetric
+    positive definite, x, y, z order) with the nine entries of G smooth standardised
+    noise (periodic Gaussian of `smooth` voxels); absorption mu in [mu_lo, mu_hi]
+    from another such field mapped through tanh; a complex Gaussian random source."""
+    rng = np.random.default_rng(seed)
+    ks = np.meshgrid(*[np.fft.fftfreq(n) for n in shape], indexing="ij")
+    filt = np.exp(-2 * (np.pi * smooth) ** 2 * sum(k ** 2 for k in ks))
+
+    def field():
+        g = np.real(np.fft.ifftn(np.fft.fftn(rng.normal(size=shape)) * filt))
+        return (g - g.mean()) / (g.std() + 1e-300)
+
+    G = np.stack([np.stack([field() for _ in range(3)], axis=-1) for _ in range(3)], axis=-2)
+    D = (np.einsum("...ab,...cb->...ac", G, G) / 3.0 + d_lo * np.eye(3)).astype(np.complex128)
+    mu = (mu_lo + (mu_hi - mu_lo) * 0.5 * (1.0 + np.tanh(field()))).astype(np.complex128)
+    src = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    return FluxDiffusionProblem(mu=mu, D=D, source=src, h=float(h))
+
+
 def batch_sizes(nprob=96, seed=4, choices=(128, 256, 512, 1024)):
     """Side lengths of the batched 2-D problems, drawn uniformly from ``choices``."""
     rng = np.random.default_rng(seed)
