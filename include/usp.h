@@ -311,47 +311,53 @@ int usp_canonical_pantograph(const double* a, const double* b, int n, double lam
 /* ---- steady diffusion in flux form with a tensor coefficient ------------
  *
  * Sec. 3.2 (Eq. diffusion-equation-matrix-form) keeps the flux J as an unknown:
- * div J + mu u = S and D^-1 J + grad u = 0 on a periodic 2-D grid of n0 x n1
- * points (axis 1, x, contiguous; axis 0, y), spacing h, spectral derivatives
- * whose Nyquist mode is zero.  Unknown x = [u; Jx; Jy], stored component-major
- * as 3 planes of n0*n1 complex values (complex64 or complex128 per dtype).
- * L keeps the derivatives and the biases mubar (smallest circle of {mu}) and
- * Dibar (smallest circle of each element of {D^-1}); V = blockdiag(mu - mubar,
- * D^-1 - Dibar) per voxel.  The system is equilibrated by a diagonal
- * S = diag(s0, s1, s2) and scaled by a real c so that ||V|| = vnorm:
- *     A = S A~ S / c,   y = S [source; 0; 0] / sqrt(c),   [u; J] = S x / sqrt(c). */
+ * div J + mu u = S and D^-1 J + grad u = 0 on a periodic 2-D or 3-D grid
+ * (shape n[0..ndim), the last axis contiguous), spacing h, spectral
+ * derivatives whose Nyquist mode is zero.  Unknown x = [u; J_x; J_y (; J_z)],
+ * stored component-major as 1 + ndim planes of n[0]*..*n[ndim-1] complex
+ * values (complex64 or complex128 per dtype); flux component k pairs with
+ * axis ndim - k (J_x with the contiguous axis).  D is given per voxel in the
+ * same (x, y, z) order.  L keeps the derivatives and the biases mubar
+ * (smallest circle of {mu}) and Dibar (smallest circle of each element of
+ * {D^-1}); V = blockdiag(mu - mubar, D^-1 - Dibar) per voxel.  The system is
+ * equilibrated by a diagonal S = diag(s) and scaled by a real c so that
+ * ||V|| = vnorm:
+ *     A = S A~ S / c,   y = S [source; 0 ..] / sqrt(c),   [u; J] = S x / sqrt(c). */
 typedef struct {
-  int n0, n1;
+  int ndim;             /* 2 or 3 */
+  int n[3];             /* grid sides (n[2] = 1 in 2-D) */
   double h;
-  double s[3];          /* equilibration */
+  double s[4];          /* equilibration: u, then J_x, J_y (, J_z) */
   double c;             /* overall scale (real, > 0) */
   double mubar[2];      /* re, im */
-  double dibar[4][2];   /* Dibar xx, xy, yx, yy (re, im) */
+  double dibar[9][2];   /* Dibar row-major ndim x ndim in (x, y, z) order (re, im) */
 } usp_flux_symbol;
 
-/* Canonical flux form (host).  Inputs: mu (n complex, 2n doubles), D (per
- * voxel the 2 x 2 tensor xx, xy, yx, yy: 4n complex), source (n complex),
- * with n = n0*n1 in row-major order.  Circles of a constant set are the value
- * itself with radius 0.  Radii dV = [[R_mu, 0, 0], [0, R_xx, R_xy],
- * [0, R_yx, R_yy]] are equilibrated symmetrically (s_i <- s_i /
- * sqrt(max_j s_i dV_ij s_j), 50 sweeps; zero rows keep s_i = 1); then
- * c = max over voxels of the spectral norm of S V~ S, divided by vnorm (1 if
- * that is 0).  Outputs (host): sym_out; bu_out (n complex) = 1 - s0^2 (mu -
- * mubar)/c; b2_out (4n complex, per voxel xx, xy, yx, yy) = I - S' (D^-1 -
- * Dibar) S' / c with S' = diag(s1, s2); y_out (3n complex).  Returns
- * USP_ERR_INVALID for NULL pointers, n0 or n1 < 2, h <= 0, vnorm outside
- * (0, 1) or a singular D, USP_ERR_NAN for non-finite input. */
-int usp_canonical_flux(const double* mu_host, const double* D_host, const double* source_host, int n0, int n1,
-                       double h, double vnorm, usp_flux_symbol* sym_out, double* bu_out, double* b2_out,
-                       double* y_out);
+/* Canonical flux form (host).  Inputs, row-major over the grid of `shape`
+ * (ndim entries, each >= 2), n voxels: mu (n complex, 2n doubles), D (per
+ * voxel the ndim x ndim tensor row-major: ndim^2 n complex), source (n
+ * complex).  Circles of a constant set are the value itself with radius 0.
+ * The radii dV = blockdiag(R_mu, [R_ab]) are equilibrated symmetrically
+ * (s_i <- s_i / sqrt(max_j s_i dV_ij s_j), 50 sweeps; zero rows keep
+ * s_i = 1); then c = max over voxels of the spectral norm of S V~ S, divided
+ * by vnorm (1 if that is 0).  Outputs (host): sym_out; bu_out (n complex) =
+ * 1 - s0^2 (mu - mubar)/c; b2_out (ndim^2 n complex, per voxel row-major) =
+ * I - S' (D^-1 - Dibar) S' / c with S' = diag(s_1 ..); y_out ((1 + ndim) n
+ * complex).  Returns USP_ERR_INVALID for NULL pointers, ndim not 2 or 3, a
+ * side < 2, h <= 0, vnorm outside (0, 1) or a singular D, USP_ERR_NAN for
+ * non-finite input. */
+int usp_canonical_flux(const double* mu_host, const double* D_host, const double* source_host, int ndim,
+                       const int* shape, double h, double vnorm, usp_flux_symbol* sym_out, double* bu_out,
+                       double* b2_out, double* y_out);
 
-/* Device workspace of a flux-form solve (n0, n1 powers of two in [8, 1024]). */
+/* Device workspace of a flux-form solve (every side a power of two in [8, 1024]). */
 int usp_flux_workspace_bytes(const usp_flux_symbol* sym, int dtype, size_t* bytes);
 
 /* Algorithm 1 on the flux-form system: per iteration t = B x + y, u = (L + I)^-1 t
- * (2-D FFTs of the three planes; per Fourier mode the inverse of the 3 x 3
- * block I + S L~(p) S / c), Delta = B (u - x), x += alpha Delta.  bu_dev
- * (n complex), b2_dev (4n complex), y_dev and x_dev (3n complex) are device
+ * (FFTs of the 1 + ndim planes; per Fourier mode the inverse of the
+ * (1 + ndim) x (1 + ndim) block I + S L~(p) S / c), Delta = B (u - x),
+ * x += alpha Delta.  bu_dev (n complex), b2_dev (ndim^2 n complex), y_dev and
+ * x_dev ((1 + ndim) n complex) are device
  * arrays of dtype; x_is_guess != 0 reads x as the starting point, else x
  * starts at 0.  Every check_every iterations (and at maxit) the FP64 relative
  * residual ||y - A x|| / ||y|| is computed; below tol the solve stops with

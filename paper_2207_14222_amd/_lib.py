@@ -58,8 +58,8 @@ class usp_batch_result(ct.Structure):
 
 
 class usp_flux_symbol(ct.Structure):
-    _fields_ = [("n0", ct.c_int), ("n1", ct.c_int), ("h", ct.c_double), ("s", ct.c_double * 3),
-                ("c", ct.c_double), ("mubar", ct.c_double * 2), ("dibar", (ct.c_double * 2) * 4)]
+    _fields_ = [("ndim", ct.c_int), ("n", ct.c_int * 3), ("h", ct.c_double), ("s", ct.c_double * 4),
+                ("c", ct.c_double), ("mubar", ct.c_double * 2), ("dibar", (ct.c_double * 2) * 9)]
 
 
 class usp_gather(ct.Structure):
@@ -130,7 +130,7 @@ def lib():
     L.usp_eigs.argtypes = [P, I, I, P, D, I, D, I, P, DP, DP, P, ct.c_size_t, IP, IP]
     L.usp_hermitian_eig.argtypes = [I, DP, DP, DP]
     FS = ct.POINTER(usp_flux_symbol)
-    L.usp_canonical_flux.argtypes = [DP, DP, DP, I, I, D, D, FS, DP, DP, DP]
+    L.usp_canonical_flux.argtypes = [DP, DP, DP, I, IP, D, D, FS, DP, DP, DP]
     L.usp_flux_workspace_bytes.argtypes = [FS, I, ct.POINTER(ct.c_size_t)]
     L.usp_flux_solve.argtypes = [FS, I, P, P, P, P, I, D, D, I, I, P, ct.c_size_t, P, IP, DP, I, DP, I, IP]
     L.usp_flux_residual.argtypes = [FS, I, P, P, P, P, P, ct.c_size_t, P, DP]

@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "../../include/usp.h"
+#include "hermitian.hpp"
 
 namespace {
 
@@ -307,8 +308,8 @@ extern "C" int usp_canonical_pantograph(const double* a, const double* b, int n,
 }
 
 // Steady diffusion in flux form (Sec. 3.2, Eq. diffusion-equation-matrix-form)
-// on a 2-D grid: biases from smallest circles, symmetric equilibration of the
-// radii, c from the largest per-voxel spectral norm of S V~ S.
+// on a 2-D or 3-D grid: biases from smallest circles, symmetric equilibration
+// of the radii, c from the largest per-voxel spectral norm of S V~ S.
 namespace {
 void circle_of(const std::vector<double>& pts, double* centre, double* R, int* rc) {
   const size_t n = pts.size() / 2;
@@ -323,31 +324,69 @@ void circle_of(const std::vector<double>& pts, double* centre, double* R, int* r
   }
   *rc = usp_smallest_circle(pts.data(), n, USP_BIAS_COMPLEX, centre, R);
 }
+
+typedef std::complex<double> cd;
+
+// largest eigenvalue of the Hermitian H = M^H M of a d x d matrix M: exact
+// for d = 2; for d = 3 the trigonometric solution of the characteristic
+// cubic (accurate to about sqrt(eps) where the top two are close) or, with
+// exact = true, cyclic Jacobi
+double top_gram_eig(int d, const cd* M, bool exact) {
+  cd H[9];
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      cd acc = 0.0;
+      for (int k = 0; k < d; ++k) acc += std::conj(M[k * d + i]) * M[k * d + j];
+      H[i * d + j] = acc;
+    }
+  if (d == 2) {
+    const double p = H[0].real(), r = H[3].real();
+    return 0.5 * (p + r) + std::sqrt(0.25 * (p - r) * (p - r) + std::norm(H[1]));
+  }
+  if (exact) {
+    std::vector<cd> a(H, H + 9);
+    std::vector<double> w;
+    std::vector<cd> Z;
+    usp_host::hermitian_jacobi(3, a, w, Z);
+    return w[2];
+  }
+  const double q = (H[0].real() + H[4].real() + H[8].real()) / 3.0;
+  const double p1 = std::norm(H[1]) + std::norm(H[2]) + std::norm(H[5]);
+  const double d0 = H[0].real() - q, d1 = H[4].real() - q, d2 = H[8].real() - q;
+  const double p2 = d0 * d0 + d1 * d1 + d2 * d2 + 2.0 * p1;
+  if (!(p2 > 0.0)) return q;
+  const double pp = std::sqrt(p2 / 6.0);
+  // det((H - q I) / pp) / 2, real for Hermitian H
+  const cd b00 = d0 / pp, b11 = d1 / pp, b22 = d2 / pp, b01 = H[1] / pp, b02 = H[2] / pp, b12 = H[5] / pp;
+  const cd det = b00 * (b11 * b22 - b12 * std::conj(b12)) - b01 * (std::conj(b01) * b22 - b12 * std::conj(b02)) +
+                 b02 * (std::conj(b01) * std::conj(b12) - b11 * std::conj(b02));
+  const double r = std::max(-1.0, std::min(1.0, 0.5 * det.real()));
+  return q + 2.0 * pp * std::cos(std::acos(r) / 3.0);
+}
 }  // namespace
 
-extern "C" int usp_canonical_flux(const double* mu, const double* D, const double* src, int n0, int n1, double h,
-                                  double vnorm, usp_flux_symbol* sym, double* bu_out, double* b2_out,
+extern "C" int usp_canonical_flux(const double* mu, const double* D, const double* src, int ndim, const int* shape,
+                                  double h, double vnorm, usp_flux_symbol* sym, double* bu_out, double* b2_out,
                                   double* y_out) {
-  if (!mu || !D || !src || !sym || !bu_out || !b2_out || !y_out || n0 < 2 || n1 < 2 || !(h > 0.0) ||
-      !(vnorm > 0.0 && vnorm < 1.0))
+  if (!mu || !D || !src || !shape || !sym || !bu_out || !b2_out || !y_out || (ndim != 2 && ndim != 3) ||
+      !(h > 0.0) || !(vnorm > 0.0 && vnorm < 1.0))
     return USP_ERR_INVALID;
-  const size_t n = (size_t)n0 * n1;
+  const int d = ndim, dd = ndim * ndim;
+  size_t n = 1;
+  for (int a = 0; a < d; ++a) {
+    if (shape[a] < 2) return USP_ERR_INVALID;
+    n *= (size_t)shape[a];
+  }
   for (size_t i = 0; i < 2 * n; ++i)
     if (!std::isfinite(mu[i]) || !std::isfinite(src[i])) return USP_ERR_NAN;
-  for (size_t i = 0; i < 8 * n; ++i)
+  for (size_t i = 0; i < 2 * dd * n; ++i)
     if (!std::isfinite(D[i])) return USP_ERR_NAN;
-  using cd = std::complex<double>;
   // D^-1 per voxel
-  std::vector<cd> Di(4 * n);
+  std::vector<cd> Di((size_t)dd * n);
   for (size_t v = 0; v < n; ++v) {
-    const cd a(D[8 * v], D[8 * v + 1]), b(D[8 * v + 2], D[8 * v + 3]);
-    const cd c(D[8 * v + 4], D[8 * v + 5]), d(D[8 * v + 6], D[8 * v + 7]);
-    const cd det = a * d - b * c;
-    if (det == cd(0.0, 0.0)) return USP_ERR_INVALID;
-    Di[4 * v + 0] = d / det;
-    Di[4 * v + 1] = -b / det;
-    Di[4 * v + 2] = -c / det;
-    Di[4 * v + 3] = a / det;
+    cd m[9];
+    for (int e = 0; e < dd; ++e) m[e] = cd(D[2 * (dd * v + e)], D[2 * (dd * v + e) + 1]);
+    if (!usp_host::small_inverse(d, m, &Di[(size_t)dd * v])) return USP_ERR_INVALID;
   }
   int rc = 0;
   double mub[2], Rmu;
@@ -356,54 +395,71 @@ extern "C" int usp_canonical_flux(const double* mu, const double* D, const doubl
     circle_of(pts, mub, &Rmu, &rc);
     if (rc) return rc;
   }
-  cd dib[4];
-  double R2[4];
-  for (int e = 0; e < 4; ++e) {
+  cd dib[9];
+  double R2[9];
+  for (int e = 0; e < dd; ++e) {
     std::vector<double> pts(2 * n);
     for (size_t v = 0; v < n; ++v) {
-      pts[2 * v] = Di[4 * v + e].real();
-      pts[2 * v + 1] = Di[4 * v + e].imag();
+      pts[2 * v] = Di[(size_t)dd * v + e].real();
+      pts[2 * v + 1] = Di[(size_t)dd * v + e].imag();
     }
     double cc[2];
     circle_of(pts, cc, &R2[e], &rc);
     if (rc) return rc;
     dib[e] = cd(cc[0], cc[1]);
   }
-  // symmetric infinity-norm equilibration of the radii
-  const double dV[3][3] = {{Rmu, 0.0, 0.0}, {0.0, R2[0], R2[1]}, {0.0, R2[2], R2[3]}};
-  double s[3] = {1.0, 1.0, 1.0};
+  // symmetric infinity-norm equilibration of the radii blockdiag(R_mu, [R_ab])
+  double dV[4][4] = {{0.0}};
+  dV[0][0] = Rmu;
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) dV[1 + a][1 + b] = R2[a * d + b];
+  double s[4] = {1.0, 1.0, 1.0, 1.0};
   for (int sweep = 0; sweep < 50; ++sweep)
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i <= d; ++i) {
       double r = 0.0;
-      for (int j = 0; j < 3; ++j) r = std::max(r, s[i] * dV[i][j] * s[j]);
+      for (int j = 0; j <= d; ++j) r = std::max(r, s[i] * dV[i][j] * s[j]);
       if (r > 0.0) s[i] /= std::sqrt(r);
     }
-  // c = max over voxels of ||S V~ S||_2 / vnorm
+  // c = max over voxels of ||S V~ S||_2 / vnorm: a fast estimate per voxel,
+  // then the exact norm wherever the estimate comes near the maximum
   const cd mubar(mub[0], mub[1]);
-  double vmax = 0.0;
-  auto v2 = [&](size_t v, int e) {
-    const int a = e / 2, b = e % 2;
-    return s[1 + a] * s[1 + b] * (Di[4 * v + e] - dib[e]);
+  auto v2 = [&](size_t v, cd* M) {
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b)
+        M[a * d + b] = s[1 + a] * s[1 + b] * (Di[(size_t)dd * v + a * d + b] - dib[a * d + b]);
   };
+  std::vector<double> est(n);
+  double emax = 0.0;
   for (size_t v = 0; v < n; ++v) {
     const double vu = s[0] * s[0] * std::abs(cd(mu[2 * v], mu[2 * v + 1]) - mubar);
-    const cd m00 = v2(v, 0), m01 = v2(v, 1), m10 = v2(v, 2), m11 = v2(v, 3);
-    // largest eigenvalue of M^H M = [[p, q], [conj q, r]]
-    const double p = std::norm(m00) + std::norm(m10), r = std::norm(m01) + std::norm(m11);
-    const cd q = std::conj(m00) * m01 + std::conj(m10) * m11;
-    const double lmax = 0.5 * (p + r) + std::sqrt(0.25 * (p - r) * (p - r) + std::norm(q));
-    vmax = std::max(vmax, std::max(vu, std::sqrt(std::max(lmax, 0.0))));
+    cd M[9];
+    v2(v, M);
+    const double nv = std::sqrt(std::max(top_gram_eig(d, M, false), 0.0));
+    est[v] = std::max(vu, nv);
+    emax = std::max(emax, est[v]);
+  }
+  double vmax = emax;
+  if (d == 3) {
+    vmax = 0.0;
+    for (size_t v = 0; v < n; ++v) {
+      if (est[v] < emax * (1.0 - 1e-6)) continue;
+      const double vu = s[0] * s[0] * std::abs(cd(mu[2 * v], mu[2 * v + 1]) - mubar);
+      cd M[9];
+      v2(v, M);
+      vmax = std::max(vmax, std::max(vu, std::sqrt(std::max(top_gram_eig(d, M, true), 0.0))));
+    }
   }
   double c = vmax / vnorm;
   if (!(c > 0.0)) c = 1.0;
-  sym->n0 = n0;
-  sym->n1 = n1;
+  *sym = usp_flux_symbol{};
+  sym->ndim = d;
+  for (int a = 0; a < 3; ++a) sym->n[a] = a < d ? shape[a] : 1;
   sym->h = h;
-  for (int k = 0; k < 3; ++k) sym->s[k] = s[k];
+  for (int k = 0; k <= d; ++k) sym->s[k] = s[k];
   sym->c = c;
   sym->mubar[0] = mub[0];
   sym->mubar[1] = mub[1];
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < dd; ++e) {
     sym->dibar[e][0] = dib[e].real();
     sym->dibar[e][1] = dib[e].imag();
   }
@@ -412,15 +468,16 @@ extern "C" int usp_canonical_flux(const double* mu, const double* D, const doubl
     const cd bu = 1.0 - s[0] * s[0] * (cd(mu[2 * v], mu[2 * v + 1]) - mubar) / c;
     bu_out[2 * v] = bu.real();
     bu_out[2 * v + 1] = bu.imag();
-    for (int e = 0; e < 4; ++e) {
-      const cd b = ((e == 0 || e == 3) ? 1.0 : 0.0) - v2(v, e) / c;
-      b2_out[8 * v + 2 * e] = b.real();
-      b2_out[8 * v + 2 * e + 1] = b.imag();
+    cd M[9];
+    v2(v, M);
+    for (int e = 0; e < dd; ++e) {
+      const cd b = ((e / d == e % d) ? 1.0 : 0.0) - M[e] / c;
+      b2_out[2 * (dd * v + e)] = b.real();
+      b2_out[2 * (dd * v + e) + 1] = b.imag();
     }
     y_out[2 * v] = s[0] * src[2 * v] * rsc;
     y_out[2 * v + 1] = s[0] * src[2 * v + 1] * rsc;
-    y_out[2 * (n + v)] = y_out[2 * (n + v) + 1] = 0.0;
-    y_out[2 * (2 * n + v)] = y_out[2 * (2 * n + v) + 1] = 0.0;
+    for (int k = 1; k <= d; ++k) y_out[2 * (k * n + v)] = y_out[2 * (k * n + v) + 1] = 0.0;
   }
   return 0;
 }

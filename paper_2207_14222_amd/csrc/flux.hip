@@ -1,15 +1,17 @@
 // C ABI of steady diffusion in flux form (Sec. 3.2, Eq.
-// diffusion-equation-matrix-form): workspace layout, the fixed-point solve
-// (Algorithm 1 on the 3-component system) and its FP64 residual.
+// diffusion-equation-matrix-form) on 2-D and 3-D grids: workspace layout, the
+// fixed-point solve (Algorithm 1 on the [u; J] system) and its FP64 residual.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <string>
 #include <vector>
 
 #include "../../include/usp.h"
 #include "flux.hpp"
+#include "hermitian.hpp"
 #include "op.hpp"
 
 using namespace usp;
@@ -21,29 +23,39 @@ constexpr int kFxHist = 1 << 16;   // device ring of ||Delta||^2 values
 constexpr int kFxRows = 32;        // ring of per-iteration partial rows, summed in batches
 
 struct FxLayout {
-  size_t t = 0, S = 0, part = 0, hist = 0, scal = 0, tw0f = 0, tw0d = 0, tw1f = 0, tw1d = 0, total = 0;
+  size_t t = 0, S = 0, part = 0, hist = 0, scal = 0, twf[3] = {0, 0, 0}, twd[3] = {0, 0, 0}, total = 0;
   long pitch = 0;
 };
 
 int fx_check(const usp_flux_symbol* sym, int dtype) {
   if (!sym) return fail(USP_ERR_INVALID, "symbol is NULL");
   if (dtype != USP_C64 && dtype != USP_C128) return fail(USP_ERR_INVALID, "dtype must be USP_C64 or USP_C128");
-  if (!pow2_in_range(sym->n0) || !pow2_in_range(sym->n1))
-    return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux grid sides must be powers of two in [8, 1024]");
+  if (sym->ndim != 2 && sym->ndim != 3) return fail(USP_ERR_INVALID, "ndim must be 2 or 3");
+  for (int a = 0; a < sym->ndim; ++a)
+    if (!pow2_in_range(sym->n[a]))
+      return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux grid sides must be powers of two in [8, 1024]");
   if (!(sym->h > 0.0) || !(sym->c > 0.0)) return fail(USP_ERR_INVALID, "h and c must be positive");
   return 0;
 }
 
-// blocks of the row kernel for a row length n1 (rows of n0)
-int fx_row_blocks(int n0, int n1) {
+long fx_voxels(const usp_flux_symbol* sym) {
+  long n = 1;
+  for (int a = 0; a < sym->ndim; ++a) n *= sym->n[a];
+  return n;
+}
+
+// grid rows along the contiguous axis, and blocks of the row kernel
+long fx_nrows(const usp_flux_symbol* sym) { return fx_voxels(sym) / sym->n[sym->ndim - 1]; }
+int fx_row_blocks(const usp_flux_symbol* sym) {
   int lpb = 1;
-  with_n(n1, [&](auto NC) { lpb = FxRow<decltype(NC)::value>::LPB; });
-  return (n0 + lpb - 1) / lpb;
+  with_n(sym->n[sym->ndim - 1], [&](auto NC) { lpb = FxRow<decltype(NC)::value>::LPB; });
+  return (int)((fx_nrows(sym) + lpb - 1) / lpb);
 }
 
 FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
   FxLayout L;
-  const long N = (long)sym->n0 * sym->n1;
+  const long N = fx_voxels(sym);
+  const int np = sym->ndim + 1;
   const size_t es = dtype == USP_C64 ? 8 : 16;
   size_t off = 0;
   auto take = [&](size_t b) {
@@ -51,41 +63,46 @@ FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
     off = align_up(off + b);
     return o;
   };
-  L.pitch = fx_row_blocks(sym->n0, sym->n1);
-  L.t = take(3 * N * es);
-  L.S = take(3 * N * 16);
+  L.pitch = fx_row_blocks(sym);
+  L.t = take(np * N * es);
+  L.S = take(np * N * 16);
   L.part = take(sizeof(double) * (kFxRows + 2) * L.pitch);
   L.hist = take(sizeof(double) * kFxHist);
   L.scal = take(sizeof(double) * 64);
-  L.tw0f = take(sizeof(float2) * sym->n0);
-  L.tw0d = take(sizeof(double2) * sym->n0);
-  L.tw1f = take(sizeof(float2) * sym->n1);
-  L.tw1d = take(sizeof(double2) * sym->n1);
+  for (int a = 0; a < sym->ndim; ++a) {
+    L.twf[a] = take(sizeof(float2) * sym->n[a]);
+    L.twd[a] = take(sizeof(double2) * sym->n[a]);
+  }
   L.total = off;
   return L;
 }
 
-FluxSym fx_sym(const usp_flux_symbol* s) {
-  FluxSym f;
+int fx_sym(const usp_flux_symbol* s, FluxSym* f) {
+  const int d = s->ndim;
+  *f = FluxSym{};
   const double ic = 1.0 / s->c;
-  f.A[0] = 1.0 + s->s[0] * s->s[0] * s->mubar[0] * ic;
-  f.A[1] = s->s[0] * s->s[0] * s->mubar[1] * ic;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
+  f->A[0] = 1.0 + s->s[0] * s->s[0] * s->mubar[0] * ic;
+  f->A[1] = s->s[0] * s->s[0] * s->mubar[1] * ic;
+  std::complex<double> E[9], Ei[9];
+  for (int a = 0; a < d; ++a)
+    for (int b = 0; b < d; ++b) {
       const double w = s->s[1 + a] * s->s[1 + b] * ic;
-      f.E[2 * a + b][0] = (a == b ? 1.0 : 0.0) + w * s->dibar[2 * a + b][0];
-      f.E[2 * a + b][1] = w * s->dibar[2 * a + b][1];
+      E[a * d + b] = std::complex<double>((a == b ? 1.0 : 0.0) + w * s->dibar[a * d + b][0],
+                                          w * s->dibar[a * d + b][1]);
     }
-  const double(*E)[2] = f.E;
-  f.dE[0] = (E[0][0] * E[3][0] - E[0][1] * E[3][1]) - (E[1][0] * E[2][0] - E[1][1] * E[2][1]);
-  f.dE[1] = (E[0][0] * E[3][1] + E[0][1] * E[3][0]) - (E[1][0] * E[2][1] + E[1][1] * E[2][0]);
-  f.q1 = s->s[0] * s->s[1] * ic;
-  f.q2 = s->s[0] * s->s[2] * ic;
-  f.pscale0 = 2.0 * M_PI / (s->n0 * s->h);
-  f.pscale1 = 2.0 * M_PI / (s->n1 * s->h);
-  f.n0 = s->n0;
-  f.n1 = s->n1;
-  return f;
+  if (!usp_host::small_inverse(d, E, Ei)) return fail(USP_ERR_INVALID, "I + S' Dibar S' / c is singular");
+  for (int e = 0; e < d * d; ++e) {
+    f->E[e][0] = E[e].real();
+    f->E[e][1] = E[e].imag();
+    f->Einv[e][0] = Ei[e].real();
+    f->Einv[e][1] = Ei[e].imag();
+  }
+  for (int k = 0; k < d; ++k) f->q[k] = s->s[0] * s->s[1 + k] * ic;
+  for (int a = 0; a < 3; ++a) {
+    f->n[a] = a < d ? s->n[a] : 1;
+    f->pscale[a] = a < d ? 2.0 * M_PI / (s->n[a] * s->h) : 0.0;
+  }
+  return 0;
 }
 
 struct FxRun {
@@ -94,23 +111,22 @@ struct FxRun {
   FxLayout L;
   char* ws;
   hipStream_t st;
-  long N;
+  long N;        // voxels
+  long nrows;    // grid rows along the contiguous axis
+  int d;
   template <class C> C* t() const { return (C*)(ws + L.t); }
   double2* S() const { return (double2*)(ws + L.S); }
   double* part() const { return (double*)(ws + L.part); }
   double* hist() const { return (double*)(ws + L.hist); }
   double* scal() const { return (double*)(ws + L.scal); }
-  template <class C> const C* tw0() const;
-  template <class C> const C* tw1() const;
+  template <class C> const C* tw(int a) const;
 };
-template <> const float2* FxRun::tw0<float2>() const { return (const float2*)(ws + L.tw0f); }
-template <> const double2* FxRun::tw0<double2>() const { return (const double2*)(ws + L.tw0d); }
-template <> const float2* FxRun::tw1<float2>() const { return (const float2*)(ws + L.tw1f); }
-template <> const double2* FxRun::tw1<double2>() const { return (const double2*)(ws + L.tw1d); }
+template <> const float2* FxRun::tw<float2>(int a) const { return (const float2*)(ws + L.twf[a]); }
+template <> const double2* FxRun::tw<double2>(int a) const { return (const double2*)(ws + L.twd[a]); }
 
 int fx_twiddles(const FxRun& R) {
-  for (int ax = 0; ax < 2; ++ax) {
-    const int n = ax == 0 ? R.sym->n0 : R.sym->n1;
+  for (int ax = 0; ax < R.d; ++ax) {
+    const int n = R.sym->n[ax];
     std::vector<float2> tf(n);
     std::vector<double2> td(n);
     for (int k = 0; k < n; ++k) {
@@ -121,41 +137,86 @@ int fx_twiddles(const FxRun& R) {
       tf[k].x = (float)c;
       tf[k].y = (float)s;
     }
-    HIPCHK(hipMemcpyAsync(R.ws + (ax == 0 ? R.L.tw0f : R.L.tw1f), tf.data(), n * sizeof(float2),
-                          hipMemcpyHostToDevice, R.st));
-    HIPCHK(hipMemcpyAsync(R.ws + (ax == 0 ? R.L.tw0d : R.L.tw1d), td.data(), n * sizeof(double2),
-                          hipMemcpyHostToDevice, R.st));
+    HIPCHK(hipMemcpyAsync(R.ws + R.L.twf[ax], tf.data(), n * sizeof(float2), hipMemcpyHostToDevice, R.st));
+    HIPCHK(hipMemcpyAsync(R.ws + R.L.twd[ax], td.data(), n * sizeof(double2), hipMemcpyHostToDevice, R.st));
   }
   HIPCHK(hipStreamSynchronize(R.st));
   return 0;
 }
 
-// y-axis pass with the per-mode block: (L + I)^-1 (inv) or L, on the 3 planes of d
+// axis-0 pass with the per-mode block: (L + I)^-1 (inv) or L, on the planes of d
 template <class C>
-int fx_col(const FxRun& R, C* d, bool inv) {
-  const bool ok = with_n(R.sym->n0, [&](auto NC) {
-    constexpr int N = decltype(NC)::value;
-    using G = FxCol<C, N>;
-    const dim3 grid((unsigned)(R.sym->n1 / G::W));
-    if (inv)
-      hipLaunchKernelGGL((k_fx_col<C, N, true>), grid, dim3(G::THREADS), 0, R.st, d, R.tw0<C>(), R.fs);
-    else
-      hipLaunchKernelGGL((k_fx_col<C, N, false>), grid, dim3(G::THREADS), 0, R.st, d, R.tw0<C>(), R.fs);
-  });
+int fx_col(const FxRun& R, C* data, bool inv) {
+  const long ncols = R.N / R.sym->n[0];
+  auto go = [&](auto DC) {
+    constexpr int D = decltype(DC)::value;
+    return with_n(R.sym->n[0], [&](auto NC) {
+      constexpr int N = decltype(NC)::value;
+      using G = FxCol<C, N, D + 1>;
+      const dim3 grid((unsigned)(ncols / G::W));
+      if (inv)
+        hipLaunchKernelGGL((k_fx_col<C, N, D, true>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0), R.fs);
+      else
+        hipLaunchKernelGGL((k_fx_col<C, N, D, false>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0), R.fs);
+    });
+  };
+  const bool ok = R.d == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux column pass");
   LAUNCHCHK("k_fx_col");
   return 0;
 }
 
-// x-axis pass in the given mode
+// 3-D: FFT (DIR -1) or inverse FFT (+1) along axis 1 of every plane (batch of
+// planes x n0 slabs, column tiles along the contiguous axis)
+template <class C, int DIR>
+int fx_mid(const FxRun& R, C* data) {
+  const int n1 = R.sym->n[1], n2 = R.sym->n[2];
+  const int batch = (R.d + 1) * R.sym->n[0];
+  bool launched = false;
+  const bool ok = with_n(n1, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int E = PassPlan<N>::E;
+    auto go = [&](auto WC) {
+      constexpr int W = decltype(WC)::value;
+      if constexpr (s_width_ok<C>(N, W, E)) {
+        if (launched || n2 % W) return;
+        hipLaunchKernelGGL((k_spass<C, N, W, DIR < 0 ? S_FWD : S_INV>), dim3(n2 / W, batch), dim3(W * (N / E)), 0,
+                           R.st, data, R.tw<C>(1), (long)n2, SymArgs{});
+        launched = true;
+      }
+    };
+    go(std::integral_constant<int, sizeof(C) == 8 ? 16 : 8>{});
+    go(std::integral_constant<int, 8>{});
+    go(std::integral_constant<int, 4>{});
+  });
+  if (!ok || !launched) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux middle-axis pass");
+  LAUNCHCHK("k_spass");
+  return 0;
+}
+
+// (L + I)^-1 (inv) or L between the contiguous-axis passes
+template <class C>
+int fx_symbol(const FxRun& R, C* data, bool inv) {
+  int rc;
+  if (R.d == 3 && (rc = fx_mid<C, -1>(R, data))) return rc;
+  if ((rc = fx_col<C>(R, data, inv))) return rc;
+  if (R.d == 3 && (rc = fx_mid<C, +1>(R, data))) return rc;
+  return 0;
+}
+
+// contiguous-axis pass in the given mode
 template <class Cc, class Cx, int MODE>
 int fx_row(const FxRun& R, Cc* spec, Cx* x, const Cx* y, const Cx* bu, const Cx* b2, double alpha, int has_x,
            double* row0, double* row1) {
-  const bool ok = with_n(R.sym->n1, [&](auto NC) {
-    constexpr int N = decltype(NC)::value;
-    hipLaunchKernelGGL((k_fx_row<Cc, Cx, N, MODE>), dim3((unsigned)R.L.pitch), dim3(3 * FxRow<N>::G), 0, R.st,
-                       spec, x, y, bu, b2, R.tw1<Cc>(), alpha, R.sym->n0, has_x, row0, row1);
-  });
+  auto go = [&](auto DC) {
+    constexpr int D = decltype(DC)::value;
+    return with_n(R.sym->n[R.d - 1], [&](auto NC) {
+      constexpr int N = decltype(NC)::value;
+      hipLaunchKernelGGL((k_fx_row<Cc, Cx, N, D, MODE>), dim3((unsigned)R.L.pitch), dim3((D + 1) * FxRow<N>::G), 0,
+                         R.st, spec, x, y, bu, b2, R.tw<Cc>(R.d - 1), alpha, R.nrows, has_x, row0, row1);
+    });
+  };
+  const bool ok = R.d == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux row pass");
   LAUNCHCHK("k_fx_row");
   return 0;
@@ -175,7 +236,7 @@ int fx_residual(const FxRun& R, const C* bu, const C* b2, const C* y, const C* x
   int rc;
   double* r0 = R.part() + kFxRows * R.L.pitch;
   if ((rc = fx_row<double2, C, FX_RFWD>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, nullptr, nullptr))) return rc;
-  if ((rc = fx_col<double2>(R, R.S(), false))) return rc;
+  if ((rc = fx_symbol<double2>(R, R.S(), false))) return rc;
   if ((rc = fx_row<double2, C, FX_RINV>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, r0, r0 + R.L.pitch))) return rc;
   if ((rc = fx_sum(R, kFxRows, 2, kFxRows + 2, R.scal(), 0, 2))) return rc;
   double h[2];
@@ -191,7 +252,7 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
              int hist_true_cap, int* n_true_out) {
   int rc;
   C* t = R.t<C>();
-  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * 3 * R.N, R.st));
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * (R.d + 1) * R.N, R.st));
   if ((rc = fx_row<C, C, FX_FIRST>(R, t, x, y, bu, b2, 0.0, x_is_guess ? 1 : 0, nullptr, nullptr))) return rc;
   int it = 0, ntrue = 0, status = USP_MAXIT, pulled = 0, flushed = 0, grow = 0;
   double d0 = -1.0, dprev = -1.0;
@@ -227,7 +288,7 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
     return 0;
   };
   while (it < maxit) {
-    if ((rc = fx_col<C>(R, t, true))) return rc;
+    if ((rc = fx_symbol<C>(R, t, true))) return rc;
     if ((rc = fx_row<C, C, FX_FUSED>(R, t, x, y, bu, b2, alpha, 1, R.part() + (it % kFxRows) * R.L.pitch,
                                      nullptr)))
       return rc;
@@ -261,14 +322,16 @@ int fx_begin(const usp_flux_symbol* sym, int dtype, void* ws, size_t ws_bytes, v
   int rc = fx_check(sym, dtype);
   if (rc) return rc;
   R->sym = sym;
-  R->fs = fx_sym(sym);
+  R->d = sym->ndim;
+  if ((rc = fx_sym(sym, &R->fs))) return rc;
   R->L = fx_layout(sym, dtype);
   if (!ws || ws_bytes < R->L.total)
     return fail(USP_ERR_WORKSPACE, "flux workspace too small: need " + std::to_string(R->L.total) + " bytes");
   if (((uintptr_t)ws) & 255) return fail(USP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   R->ws = (char*)ws;
   R->st = (hipStream_t)stream;
-  R->N = (long)sym->n0 * sym->n1;
+  R->N = fx_voxels(sym);
+  R->nrows = fx_nrows(sym);
   return fx_twiddles(*R);
 }
 

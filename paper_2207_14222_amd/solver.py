@@ -385,38 +385,41 @@ def hermitian_eig(a):
 
 
 def canonical_flux_host(mu, D, source, h, vnorm: float = 0.95):
-    """usp_canonical_flux (host): returns (usp_flux_symbol, bu (n0, n1), b2 (n0, n1, 2, 2), y (3, n0, n1))."""
+    """usp_canonical_flux (host) on a 2-D or 3-D grid: returns (usp_flux_symbol, bu (grid),
+    b2 (grid + (d, d)), y ((1 + d,) + grid)); D in the (x, y[, z]) order of the flux
+    components, x the contiguous axis."""
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.complex128))
     Dm = np.ascontiguousarray(np.asarray(D, dtype=np.complex128))
     src = np.ascontiguousarray(np.asarray(source, dtype=np.complex128))
-    n0, n1 = mu.shape
-    if Dm.shape != (n0, n1, 2, 2) or src.shape != (n0, n1):
-        raise ValueError("mu (n0, n1), D (n0, n1, 2, 2), source (n0, n1)")
+    d = mu.ndim
+    if d not in (2, 3) or Dm.shape != mu.shape + (d, d) or src.shape != mu.shape:
+        raise ValueError("mu (grid), D (grid + (d, d)), source (grid) on a 2-D or 3-D grid")
     sym = L.usp_flux_symbol()
-    bu = np.zeros((n0, n1), np.complex128)
-    b2 = np.zeros((n0, n1, 2, 2), np.complex128)
-    y = np.zeros((3, n0, n1), np.complex128)
+    bu = np.zeros(mu.shape, np.complex128)
+    b2 = np.zeros(mu.shape + (d, d), np.complex128)
+    y = np.zeros((1 + d,) + mu.shape, np.complex128)
+    shape = (ct.c_int * 3)(*(list(mu.shape) + [1] * (3 - d)))
     f = lambda z: _dp(z.view(np.float64))
-    L.check(L.lib().usp_canonical_flux(f(mu), f(Dm), f(src), n0, n1, float(h), float(vnorm), ct.byref(sym),
+    L.check(L.lib().usp_canonical_flux(f(mu), f(Dm), f(src), d, shape, float(h), float(vnorm), ct.byref(sym),
                                        f(bu), f(b2), f(y)))
     return sym, bu, b2, y
 
 
 class FluxOperator:
     """Steady diffusion in flux form with a tensor coefficient (usp_canonical_flux
-    on the host, then usp_flux_solve / usp_flux_residual on the device).
-    Fields are (3, n0, n1) tensors: [u; Jx; Jy] of the canonical system."""
+    on the host, then usp_flux_solve / usp_flux_residual on the device), 2-D or
+    3-D.  Fields are (1 + d,) + grid tensors: [u; Jx; Jy (; Jz)] of the
+    canonical system."""
 
     def __init__(self, mu, D, source, h, vnorm: float = 0.95, dtype=torch.complex128, device="cuda"):
         self.sym, bu, b2, y = canonical_flux_host(mu, D, source, h, vnorm)
-        n0, n1 = bu.shape
         self.device = torch.device(device)
         self.dtype = dtype
         self.dt = L.USP_C64 if dtype == torch.complex64 else L.USP_C128
         T = lambda z: torch.from_numpy(z).to(device=self.device, dtype=dtype)
         self.bu, self.b2, self.y = T(bu), T(b2), T(y)
         self.device = self.y.device          # "cuda" resolved to "cuda:<index>"
-        self.shape = (3, n0, n1)
+        self.shape = tuple(y.shape)
         nb = ct.c_size_t()
         L.check(L.lib().usp_flux_workspace_bytes(ct.byref(self.sym), self.dt, ct.byref(nb)))
         self.ws_bytes = nb.value
@@ -424,7 +427,7 @@ class FluxOperator:
 
     @property
     def s(self):
-        return np.array(self.sym.s[:])
+        return np.array(self.sym.s[:self.sym.ndim + 1])
 
     @property
     def c(self):
@@ -469,7 +472,7 @@ class FluxOperator:
     def physical(self, x):
         """[u; Jx; Jy] = S x / sqrt(c)."""
         s = torch.tensor(self.s, dtype=torch.float64, device=x.device).to(x.real.dtype)
-        return x * (s[:, None, None] / np.sqrt(self.c))
+        return x * (s.reshape((-1,) + (1,) * (x.dim() - 1)) / np.sqrt(self.c))
 
 
 @dataclass

@@ -126,9 +126,10 @@ def test_host_canonical_pantograph_matches_oracle():
 
 
 def test_host_canonical_flux_matches_oracle():
-    """Library flux-form canonicalisation (closed-form 2 x 2 spectral norms) vs
-    the oracle (numpy SVD norms), on the anisotropic ring and an isotropic case."""
-    import ctypes as ct
+    """Library flux-form canonicalisation (closed-form 2 x 2 and trigonometric
+    3 x 3 spectral norms, exact where they set c) vs the oracle (numpy SVD
+    norms), on the anisotropic ring, an isotropic case and a random 3-D
+    tensor medium."""
     from oracle import flux as F
     from paper_2207_14222_amd import _lib, media, solver
     p = media.diffusion_ring(n=64, h=0.4, radius=8.0, width=3.0, abs_rows=6, src_row=3)
@@ -139,13 +140,17 @@ def test_host_canonical_flux_matches_oracle():
     mu = np.full((n, n), 0.3, complex)
     mu[0, 0] = 2.0
     cases.append((mu, Di, np.ones((n, n)), 0.5))
+    q = media.diffusion_tensor_random3(shape=(8, 16, 32), seed=3)
+    cases.append((q.mu, q.D, q.source, q.h))
     for mu, D, src, h in cases:
+        d = mu.ndim
         cp = F.canonical_flux(mu, D, src, h)
         sym, bu, b2, y = solver.canonical_flux_host(mu, D, src, h)
+        assert sym.ndim == d and list(sym.n[:d]) == list(mu.shape)
         assert abs(sym.c - cp.c) < 1e-12 * cp.c
-        assert np.allclose(np.array(sym.s[:]), cp.s, rtol=1e-12)
+        assert np.allclose(np.array(sym.s[:d + 1]), cp.s, rtol=1e-12)
         assert abs(complex(*sym.mubar) - cp.mubar) < 1e-12 * (1 + abs(cp.mubar))
-        dib = np.array([complex(*sym.dibar[e]) for e in range(4)]).reshape(2, 2)
+        dib = np.array([complex(*sym.dibar[e]) for e in range(d * d)]).reshape(d, d)
         assert np.allclose(dib, cp.Dibar, rtol=1e-12, atol=1e-14)
         assert np.allclose(bu, cp.Buu, atol=1e-12) and np.allclose(b2, cp.B2, atol=1e-12)
         assert np.allclose(y, cp.y, rtol=1e-12, atol=1e-14)

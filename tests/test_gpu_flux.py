@@ -10,7 +10,10 @@ FP64 oracle:
 * the solve reaches the dense-LU solution on a 16 x 16 grid (768 unknowns)
   and the Schur reduction holds for the physical u;
 * at 256 x 256 the solve stops at the oracle's checkpoint (written by
-  tests/golden/make_flux_golden.py) with ||Delta|| non-increasing."""
+  tests/golden/make_flux_golden.py) with ||Delta|| non-increasing;
+* 3-D (four components): K iterates on random tensor media over grids whose
+  sides differ (every axis length from 8 to 64 in each position), the FP64
+  residual, and the solve against dense LU on an 8^3 grid."""
 import json
 import os
 
@@ -136,3 +139,40 @@ def test_invalid_arguments():
     gop = solver.FluxOperator(p.mu, p.D, p.source, p.h)
     with pytest.raises(ValueError):
         gop.residual(torch.zeros((3, 64, 32), dtype=torch.complex128, device="cuda"))
+
+
+# ---- 3-D: four components [u; Jx; Jy; Jz] -----------------------------------
+
+@pytest.mark.parametrize("shape", [(8, 16, 32), (32, 8, 16), (16, 32, 8), (16, 32, 64), (64, 8, 8)])
+@pytest.mark.parametrize("dt", ["c128", "c64"])
+def test_3d_iterates_match_oracle(shape, dt):
+    _need_gpu()
+    print(f"[gpu-case] flux 3-D iterates {shape} {dt}", flush=True)
+    p = media.diffusion_tensor_random3(shape=shape, seed=sum(shape))
+    cp, op, gop = _pair(p, torch.complex128 if dt == "c128" else torch.complex64)
+    assert gop.shape == op.shape == (4,) + shape
+    K = 25
+    xo, ho = R.iterate(op, cp.y, 0.9, K)
+    x, h = gop.iterate(alpha=0.9, K=K)
+    tol = 1e-11 if dt == "c128" else 3e-5
+    assert rel(x.cpu().numpy().astype(np.complex128), xo) < tol
+    np.testing.assert_allclose(np.sqrt(h), ho, rtol=10 * tol)
+    if dt == "c128":
+        rng = np.random.default_rng(2)
+        xr = rng.normal(size=op.shape) + 1j * rng.normal(size=op.shape)
+        rho = gop.residual(torch.from_numpy(xr).to("cuda"))
+        assert abs(rho - R.relative_residual(op, xr, cp.y)) < 1e-12 * max(1.0, rho)
+
+
+def test_3d_solution_matches_dense_lu():
+    _need_gpu()
+    print("[gpu-case] flux 3-D dense 8x8x8", flush=True)
+    p = media.diffusion_tensor_random3(shape=(8, 8, 8), seed=21)
+    cp, op, gop = _pair(p)
+    xs = np.linalg.solve(op.dense(op.apply_A), cp.y.ravel()).reshape(op.shape)
+    r = gop.solve(alpha=1.0, tol=1e-11, maxit=20000, check_every=10)
+    assert r.converged, r.status_name
+    assert rel(r.x.cpu().numpy(), xs) < 1e-8
+    assert rel(gop.physical(r.x).cpu().numpy(), op.physical(xs)) < 1e-8
+    d = np.sqrt(r.hist_pre)
+    assert np.all(np.diff(d) <= 1e-12 * d[0])
