@@ -22,7 +22,7 @@ on the solver's stream), the FP64 CPU oracle timed on a bounded sample, and
 the other workloads under "modes": BiCGSTAB and GMRES(m) on the same
 preconditioned operator, the pantograph in direct and antisymmetrised
 form, diffusion (plain vs refined), flux-form tensor diffusion on the
-256 x 256 ring, the five lowest eigenmodes of a double-ring well (512 x 512,
+256 x 256 ring and on a 128^3 random tensor medium, the five lowest eigenmodes of a double-ring well (512 x 512,
 Lanczos with CG inner solves), 96 batched
 2-D problems in one graph-captured schedule, and the learned initial guess
 on 128^3 media (--learned-train/--learned-test/--learned-epochs; the full
@@ -305,6 +305,48 @@ def bench_flux(args, log):
     return out
 
 
+def bench_flux3d(args, log):
+    """Steady anisotropic diffusion in flux form in 3-D (four components [u; Jx;
+    Jy; Jz]) on a 128^3 random tensor medium (media.diffusion_tensor_random3,
+    seed 7): complex128 solve from x = 0 at alpha = 1 to 1e-6, FP64 residual
+    every 20 iterations, and the iteration time without checks for complex128
+    and complex64.  Bytes per iteration (four launches): the two middle-axis
+    passes and the axis-0 pass read and write the 4 planes of t (3 x 8 N
+    values); the row pass reads t, x, y (3 x 4 N), b_u (N) and b2 (9 N) and
+    writes x and t (8 N): 54 N values."""
+    import torch
+    from paper_2207_14222_amd import media, solver
+    p = media.diffusion_tensor_random3(shape=(128, 128, 128), seed=7, h=0.3)
+    n = p.mu.size
+    out = {"grid": [128, 128, 128]}
+    for dname, dt, es in (("c128", torch.complex128, 16), ("c64", torch.complex64, 8)):
+        op = solver.FluxOperator(p.mu, p.D, p.source, p.h, dtype=dt)
+        iter_bytes = 54 * n * es
+        rec = {}
+        if dname == "c128":
+            op.solve(alpha=1.0, tol=1e-6, maxit=5000, check_every=20)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = op.solve(alpha=1.0, tol=1e-6, maxit=5000, check_every=20)
+            torch.cuda.synchronize()
+            rec.update({"time_ms": round((time.perf_counter() - t0) * 1e3, 2), "iterations": r.iterations,
+                        "status": r.status_name, "rho": float(r.hist_true[-1, 1])})
+        K = 50
+        op.iterate(alpha=1.0, K=5)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        op.iterate(alpha=1.0, K=K)
+        torch.cuda.synchronize()
+        us_it = (time.perf_counter() - t1) * 1e6 / K
+        rec.update({"us_per_iteration": round(us_it, 1),
+                    "model_GB/s_per_iter": round(iter_bytes / (us_it * 1e-6) / 1e9, 1)})
+        out[dname] = rec
+        del op
+        torch.cuda.empty_cache()
+    log(f"flux-form diffusion 3-D: {out}")
+    return out
+
+
 def bench_eigen(args, log):
     """Five lowest modes of the double-ring well (Sec. 4, Eq. schrodinger) on a
     512 x 512 grid, complex128: H + 5 in canonical form, shift-invert Lanczos
@@ -555,6 +597,11 @@ def main():
     if not args.no_flux:
         log("flux-form tensor diffusion (256 x 256 ring)")
         extra["flux_ring256"] = bench_flux(args, log)
+        torch.cuda.empty_cache()
+
+    if not args.no_flux:
+        log("flux-form tensor diffusion in 3-D (128^3)")
+        extra["flux3d_128"] = bench_flux3d(args, log)
         torch.cuda.empty_cache()
 
     if not args.no_eigen:

@@ -144,24 +144,39 @@ int fx_twiddles(const FxRun& R) {
   return 0;
 }
 
-// axis-0 pass with the per-mode block: (L + I)^-1 (inv) or L, on the planes of d
+// axis-0 pass with the per-mode block: (L + I)^-1 (inv) or L, on the planes of
+// data, in tiles of 2 columns (1 where the planes' tiles exceed LDS).
+// Measured: 2 columns beat 4, 8 and 16 both at 256 x 256 (more blocks in
+// flight) and at 128^3 (wider tiles, up to 128-byte segments in 1024-thread
+// blocks, ran the pass up to 1.4x slower).
 template <class C>
 int fx_col(const FxRun& R, C* data, bool inv) {
   const long ncols = R.N / R.sym->n[0];
+  bool launched = false;
   auto go = [&](auto DC) {
     constexpr int D = decltype(DC)::value;
     return with_n(R.sym->n[0], [&](auto NC) {
       constexpr int N = decltype(NC)::value;
-      using G = FxCol<C, N, D + 1>;
-      const dim3 grid((unsigned)(ncols / G::W));
-      if (inv)
-        hipLaunchKernelGGL((k_fx_col<C, N, D, true>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0), R.fs);
-      else
-        hipLaunchKernelGGL((k_fx_col<C, N, D, false>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0), R.fs);
+      auto try_w = [&](auto WC) {
+        constexpr int W = decltype(WC)::value;
+        if constexpr (FxCol<C, N, D + 1, W>::VALID) {
+          using G = FxCol<C, N, D + 1, W>;
+          if (launched || ncols % W) return;
+          const dim3 grid((unsigned)(ncols / W));
+          if (inv)
+            hipLaunchKernelGGL((k_fx_col<C, N, D, W, true>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0), R.fs);
+          else
+            hipLaunchKernelGGL((k_fx_col<C, N, D, W, false>), grid, dim3(G::THREADS), 0, R.st, data, R.tw<C>(0),
+                               R.fs);
+          launched = true;
+        }
+      };
+      try_w(std::integral_constant<int, 2>{});
+      try_w(std::integral_constant<int, 1>{});
     });
   };
   const bool ok = R.d == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
-  if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux column pass");
+  if (!ok || !launched) return fail(USP_ERR_UNSUPPORTED_SHAPE, "flux column pass");
   LAUNCHCHK("k_fx_col");
   return 0;
 }

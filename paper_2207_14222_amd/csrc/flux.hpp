@@ -64,18 +64,18 @@ template <> struct FxColPlan<256> { using P = Plan<8, 8, 4>; };
 template <> struct FxColPlan<512> { using P = Plan<8, 8, 8>; };
 template <> struct FxColPlan<1024> { using P = Plan<8, 8, 4, 4>; };
 
-// Column kernel geometry for NP planes: W = 2 columns per block (more blocks
-// in flight beat wider row segments at these sizes; measured), 1 where NP
-// [N][W+1] tiles exceed LDS; 4 elements per thread when NP W N/4 threads fit
-// a block, else 8; twiddles in LDS when they fit beside the tiles.
-template <class C, int N, int NP> struct FxCol {
-  static constexpr int tile_bytes(int w) { return NP * N * (w + 1) * (int)sizeof(C); }
-  static constexpr int W = tile_bytes(2) <= 160 * 1024 ? 2 : 1;
+// Column kernel geometry for NP planes and W columns per block (the host
+// launches W = 2, or 1 where the tiles exceed LDS); 4 elements per thread when NP W N/4
+// threads fit a block, else 8; twiddles in LDS when they fit beside the tiles.
+template <class C, int N, int NP, int W_> struct FxCol {
+  static constexpr int W = W_;
+  static constexpr int tile_bytes = NP * N * (W + 1) * (int)sizeof(C);
   static constexpr bool LINE = NP * W * (N / 4) <= 1024;
   static constexpr int E = LINE ? 4 : 8, T = N / E;
   using P = typename std::conditional<LINE, typename LinePlan<N>::P, typename FxColPlan<N>::P>::type;
   static constexpr int THREADS = NP * W * T;
-  static constexpr bool TWL = tile_bytes(W) + N * (int)sizeof(C) <= 160 * 1024;
+  static constexpr bool VALID = tile_bytes <= 160 * 1024 && THREADS <= 1024 && W * (int)sizeof(C) <= 128 && W <= N;
+  static constexpr bool TWL = tile_bytes + N * (int)sizeof(C) <= 160 * 1024;
 };
 
 // z <- M(p)^-1 z (INV) or (M(p) - I) z, times sc, for one mode's D + 1 plane
@@ -179,11 +179,11 @@ __device__ __forceinline__ double fx_wavenumber(int k, int n, double scale) {
 // block ((L + I)^-1 if INV, else L) times 1/n_total, inverse FFT.  Plane k,
 // position p, column col (an index over the other axes, the last one
 // fastest) lives at data[k n + p ncols + col]; the grid has ncols / W blocks
-// of FxCol::THREADS threads.
-template <class C, int N, int D, bool INV>
-__global__ void __launch_bounds__((FxCol<C, N, D + 1>::THREADS))
+// of FxCol::THREADS threads (FxCol::VALID).
+template <class C, int N, int D, int W_, bool INV>
+__global__ void __launch_bounds__((FxCol<C, N, D + 1, W_>::THREADS))
 k_fx_col(C* __restrict__ data, const C* __restrict__ tw, FluxSym fs) {
-  using G = FxCol<C, N, D + 1>;
+  using G = FxCol<C, N, D + 1, W_>;
   constexpr int W = G::W, E = G::E, T = G::T, NP = D + 1;
   __shared__ C tiles[NP * N * (W + 1)];
   __shared__ C tws[G::TWL ? N : 1];
