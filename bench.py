@@ -267,11 +267,31 @@ def bench_pantograph(args, log):
     return out
 
 
+def _flux_refined(p, tol, k, maxit):
+    """Refined flux-form solve (complex64 inner iterations, FP64 residual and
+    update every k) from x = 0 at alpha = 1 to tol; one untimed run first."""
+    import torch
+    from paper_2207_14222_amd import solver
+    op = solver.FluxOperator(p.mu, p.D, p.source, p.h, refine=True)
+    op.solve(alpha=1.0, tol=tol, maxit=maxit, check_every=k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = op.solve(alpha=1.0, tol=tol, maxit=maxit, check_every=k)
+    torch.cuda.synchronize()
+    dtm = time.perf_counter() - t0
+    rho = op.residual(r.x)
+    del op
+    torch.cuda.empty_cache()
+    return {"time_ms": round(dtm * 1e3, 2), "iterations": r.iterations, "status": r.status_name,
+            "cycles": int(r.hist_true.shape[0]), "rho": rho, "refine_every": k}
+
+
 def bench_flux(args, log):
     """Steady anisotropic diffusion in flux form (Sec. 3.2) on the 256 x 256 ring:
     complex128 and complex64 solves from x = 0 at alpha = 1 to ||r||/||y|| < 1e-3
     (the tolerance of Table 1) and complex128 to 1e-6, the FP64 residual checked
-    every 10 iterations.  Bytes per iteration (two launches): the column pass
+    every 10 iterations, and the refined solve (complex64 inner iterations, FP64
+    refinement) to 1e-6.  Bytes per iteration (two launches): the column pass
     reads and writes the 3 planes of t (6 N values); the row pass reads t, x,
     y, b_u, b2 (3+3+3+1+4 N) and writes x and t (6 N)."""
     import torch
@@ -301,6 +321,7 @@ def bench_flux(args, log):
                 "rho": float(r.hist_true[-1, 1]), "us_per_iteration": round(us_it, 2),
                 "model_GB/s_per_iter": round(iter_bytes / (us_it * 1e-6) / 1e9, 1)}
         del op
+    out["refined_tol1e-06"] = _flux_refined(p, 1e-6, args.refine_every, 20000)
     log(f"flux-form diffusion: {out}")
     return out
 
@@ -309,7 +330,8 @@ def bench_flux3d(args, log):
     """Steady anisotropic diffusion in flux form in 3-D (four components [u; Jx;
     Jy; Jz]) on a 128^3 random tensor medium (media.diffusion_tensor_random3,
     seed 7): complex128 solve from x = 0 at alpha = 1 to 1e-6, FP64 residual
-    every 20 iterations, and the iteration time without checks for complex128
+    every 20 iterations, the refined solve (complex64 inner iterations, FP64
+    refinement) to 1e-6, and the iteration time without checks for complex128
     and complex64.  Bytes per iteration (four launches): the two middle-axis
     passes and the axis-0 pass read and write the 4 planes of t (3 x 8 N
     values); the row pass reads t, x, y (3 x 4 N), b_u (N) and b2 (9 N) and
@@ -343,6 +365,7 @@ def bench_flux3d(args, log):
         out[dname] = rec
         del op
         torch.cuda.empty_cache()
+    out["refined"] = _flux_refined(p, 1e-6, args.refine_every, 5000)
     log(f"flux-form diffusion 3-D: {out}")
     return out
 

@@ -371,6 +371,29 @@ int usp_flux_solve(const usp_flux_symbol* sym, int dtype, const void* bu_dev, co
                    size_t ws_bytes, void* stream, int* iters_out, double* hist_pre, int hist_pre_cap,
                    double* hist_true, int hist_true_cap, int* n_true_out);
 
+/* Device workspace of usp_flux_solve_refined. */
+int usp_flux_refined_workspace_bytes(const usp_flux_symbol* sym, size_t* bytes);
+
+/* Mixed-precision flux-form solve (the refinement of Sec. 2.1 applied to the
+ * system of usp_flux_solve): bu_dev, b2_dev, y_dev, x_dev are complex128
+ * device arrays laid out as for usp_flux_solve.  Each cycle computes the
+ * FP64 residual r = y - A x (its relative norm is a hist_true entry; below
+ * tol the solve stops with USP_OK), then runs up to refine_every complex64
+ * iterations of Algorithm 1 on A d = r from d = 0 (on workspace copies of
+ * B and r) and adds d to x in FP64.  The last cycle is cut to the number of
+ * iterations that the rate of ||Delta|| over the last 10 iterations predicts
+ * for reaching tol, when that is under half of refine_every.  x_is_guess:
+ * 0 starts from x = 0; 1 reads x; 2 reads x and discards it (restart from 0)
+ * if its residual is not below ||y||.  hist_pre gets the inner iterations'
+ * ||Delta||^2.  Returns USP_OK, USP_MAXIT, USP_STAGNATED (no 1% residual
+ * improvement over 8 cycles), USP_DIVERGED or an error.  Workspace: 256-byte
+ * aligned, at least usp_flux_refined_workspace_bytes.  Synchronises `stream`
+ * before returning. */
+int usp_flux_solve_refined(const usp_flux_symbol* sym, const void* bu_dev, const void* b2_dev, const void* y_dev,
+                           void* x_dev, int x_is_guess, double alpha, double tol, int maxit, int refine_every,
+                           void* ws_dev, size_t ws_bytes, void* stream, int* iters_out, double* hist_pre,
+                           int hist_pre_cap, double* hist_true, int hist_true_cap, int* n_true_out);
+
 /* FP64 relative residual ||y - A x|| / ||y|| of the flux-form system. */
 int usp_flux_residual(const usp_flux_symbol* sym, int dtype, const void* bu_dev, const void* b2_dev,
                       const void* y_dev, const void* x_dev, void* ws_dev, size_t ws_bytes, void* stream,

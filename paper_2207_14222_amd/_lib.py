@@ -33,6 +33,7 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_nn_features", "usp_nn_loss", "usp_nn_adam", "usp_nn_pack_weights", "usp_nn_to_bf16",
            "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond",
            "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual",
+           "usp_flux_refined_workspace_bytes", "usp_flux_solve_refined",
            "usp_eigs_workspace_bytes", "usp_eigs", "usp_hermitian_eig"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
@@ -134,6 +135,8 @@ def lib():
     L.usp_flux_workspace_bytes.argtypes = [FS, I, ct.POINTER(ct.c_size_t)]
     L.usp_flux_solve.argtypes = [FS, I, P, P, P, P, I, D, D, I, I, P, ct.c_size_t, P, IP, DP, I, DP, I, IP]
     L.usp_flux_residual.argtypes = [FS, I, P, P, P, P, P, ct.c_size_t, P, DP]
+    L.usp_flux_refined_workspace_bytes.argtypes = [FS, ct.POINTER(ct.c_size_t)]
+    L.usp_flux_solve_refined.argtypes = [FS, P, P, P, P, I, D, D, I, I, P, ct.c_size_t, P, IP, DP, I, DP, I, IP]
     L.usp_canonical_pantograph.argtypes = [DP, DP, I, D, D, D, DP, DP, D, SP, DP, ct.POINTER(ct.c_int32), DP, DP,
                                            DP, DP, DP]
     for name in EXPORTS:

@@ -24,6 +24,8 @@ constexpr int kFxRows = 32;        // ring of per-iteration partial rows, summed
 
 struct FxLayout {
   size_t t = 0, S = 0, part = 0, hist = 0, scal = 0, twf[3] = {0, 0, 0}, twd[3] = {0, 0, 0}, total = 0;
+  // refined solve: complex64 copies of b_u and b2, the residual and the correction
+  size_t bu32 = 0, b232 = 0, r32 = 0, d32 = 0;
   long pitch = 0;
 };
 
@@ -52,7 +54,9 @@ int fx_row_blocks(const usp_flux_symbol* sym) {
   return (int)((fx_nrows(sym) + lpb - 1) / lpb);
 }
 
-FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
+// refined: complex64 spectrum for the inner iterations plus the refinement
+// arrays (dtype is then USP_C64 for the layout of t)
+FxLayout fx_layout(const usp_flux_symbol* sym, int dtype, bool refined = false) {
   FxLayout L;
   const long N = fx_voxels(sym);
   const int np = sym->ndim + 1;
@@ -72,6 +76,12 @@ FxLayout fx_layout(const usp_flux_symbol* sym, int dtype) {
   for (int a = 0; a < sym->ndim; ++a) {
     L.twf[a] = take(sizeof(float2) * sym->n[a]);
     L.twd[a] = take(sizeof(double2) * sym->n[a]);
+  }
+  if (refined) {
+    L.bu32 = take(sizeof(float2) * N);
+    L.b232 = take(sizeof(float2) * sym->ndim * sym->ndim * N);
+    L.r32 = take(sizeof(float2) * np * N);
+    L.d32 = take(sizeof(float2) * np * N);
   }
   L.total = off;
   return L;
@@ -120,6 +130,7 @@ struct FxRun {
   double* hist() const { return (double*)(ws + L.hist); }
   double* scal() const { return (double*)(ws + L.scal); }
   template <class C> const C* tw(int a) const;
+  float2* f32(size_t off) const { return (float2*)(ws + off); }
 };
 template <> const float2* FxRun::tw<float2>(int a) const { return (const float2*)(ws + L.twf[a]); }
 template <> const double2* FxRun::tw<double2>(int a) const { return (const double2*)(ws + L.twd[a]); }
@@ -222,13 +233,13 @@ int fx_symbol(const FxRun& R, C* data, bool inv) {
 // contiguous-axis pass in the given mode
 template <class Cc, class Cx, int MODE>
 int fx_row(const FxRun& R, Cc* spec, Cx* x, const Cx* y, const Cx* bu, const Cx* b2, double alpha, int has_x,
-           double* row0, double* row1) {
+           double* row0, double* row1, const float2* dcor = nullptr, float2* r32 = nullptr) {
   auto go = [&](auto DC) {
     constexpr int D = decltype(DC)::value;
     return with_n(R.sym->n[R.d - 1], [&](auto NC) {
       constexpr int N = decltype(NC)::value;
       hipLaunchKernelGGL((k_fx_row<Cc, Cx, N, D, MODE>), dim3((unsigned)R.L.pitch), dim3((D + 1) * FxRow<N>::G), 0,
-                         R.st, spec, x, y, bu, b2, R.tw<Cc>(R.d - 1), alpha, R.nrows, has_x, row0, row1);
+                         R.st, spec, x, y, bu, b2, R.tw<Cc>(R.d - 1), alpha, R.nrows, has_x, row0, row1, dcor, r32);
     });
   };
   const bool ok = R.d == 2 ? go(std::integral_constant<int, 2>{}) : go(std::integral_constant<int, 3>{});
@@ -246,13 +257,17 @@ int fx_sum(const FxRun& R, int first, int nrows, int ring, double* out, int out_
   return 0;
 }
 
+// rho = ||y - A x|| / ||y|| in FP64.  Refined solve: dcor (complex64) is
+// first added to x in place, and r is also stored as complex64 in r32.
 template <class C>
-int fx_residual(const FxRun& R, const C* bu, const C* b2, const C* y, const C* x, double* rho) {
+int fx_residual(const FxRun& R, const C* bu, const C* b2, const C* y, const C* x, double* rho,
+                const float2* dcor = nullptr, float2* r32 = nullptr) {
   int rc;
   double* r0 = R.part() + kFxRows * R.L.pitch;
-  if ((rc = fx_row<double2, C, FX_RFWD>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, nullptr, nullptr))) return rc;
+  if ((rc = fx_row<double2, C, FX_RFWD>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, nullptr, nullptr, dcor))) return rc;
   if ((rc = fx_symbol<double2>(R, R.S(), false))) return rc;
-  if ((rc = fx_row<double2, C, FX_RINV>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, r0, r0 + R.L.pitch))) return rc;
+  if ((rc = fx_row<double2, C, FX_RINV>(R, R.S(), (C*)x, y, bu, b2, 0.0, 1, r0, r0 + R.L.pitch, nullptr, r32)))
+    return rc;
   if ((rc = fx_sum(R, kFxRows, 2, kFxRows + 2, R.scal(), 0, 2))) return rc;
   double h[2];
   HIPCHK(hipMemcpyAsync(h, R.scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, R.st));
@@ -261,25 +276,31 @@ int fx_residual(const FxRun& R, const C* bu, const C* b2, const C* y, const C* x
   return 0;
 }
 
-template <class C>
-int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_is_guess, double alpha, double tol,
-             int maxit, int check_every, int* iters_out, double* hist_pre, int hist_pre_cap, double* hist_true,
-             int hist_true_cap, int* n_true_out) {
-  int rc;
-  C* t = R.t<C>();
-  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * (R.d + 1) * R.N, R.st));
-  if ((rc = fx_row<C, C, FX_FIRST>(R, t, x, y, bu, b2, 0.0, x_is_guess ? 1 : 0, nullptr, nullptr))) return rc;
-  int it = 0, ntrue = 0, status = USP_MAXIT, pulled = 0, flushed = 0, grow = 0;
+// ||Delta||^2 history: per-iteration partial rows in a ring of kFxRows, summed
+// in batches into the device ring `hist`, pulled to the host at checks
+struct FxHist {
+  const FxRun& R;
+  double* hist_pre;
+  int hist_pre_cap;
+  int it = 0, pulled = 0, flushed = 0, grow = 0, status = USP_MAXIT;
   double d0 = -1.0, dprev = -1.0;
+  double tail[16];   // latest values (ring), for the refined solve's rate
+  int ntail = 0;
   std::vector<double> buf;
+  double* row() const { return R.part() + (it % kFxRows) * R.L.pitch; }
+  // one iteration's partial row was written at row(): advance
+  int step() {
+    ++it;
+    return it - flushed == kFxRows ? flush() : 0;
+  }
   // sum the pending partial rows of iterations [flushed, it) into the history ring
-  auto flush = [&]() -> int {
+  int flush() {
     const int m = it - flushed;
     const int e = fx_sum(R, flushed % kFxRows, m, kFxRows, R.hist(), flushed % kFxHist, kFxHist);
     flushed = it;
     return e;
-  };
-  auto pull = [&]() -> int {
+  }
+  int pull() {
     const int n = it - pulled;
     if (n <= 0) return 0;
     buf.resize(n);
@@ -298,21 +319,37 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
       grow = (dprev >= 0.0 && dd > dprev) ? grow + 1 : 0;
       dprev = dd;
       if (grow >= 3 && dd > d0 && status != USP_ERR_NAN) status = USP_DIVERGED;
+      tail[ntail++ % 16] = dd;
     }
     pulled = it;
     return 0;
-  };
-  while (it < maxit) {
+  }
+  int sync() {
+    int rc;
+    if ((rc = flush()) || (rc = pull())) return rc;
+    return 0;
+  }
+};
+
+template <class C>
+int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_is_guess, double alpha, double tol,
+             int maxit, int check_every, int* iters_out, double* hist_pre, int hist_pre_cap, double* hist_true,
+             int hist_true_cap, int* n_true_out) {
+  int rc;
+  C* t = R.t<C>();
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * (R.d + 1) * R.N, R.st));
+  if ((rc = fx_row<C, C, FX_FIRST>(R, t, x, y, bu, b2, 0.0, x_is_guess ? 1 : 0, nullptr, nullptr))) return rc;
+  FxHist H{R, hist_pre, hist_pre_cap};
+  int ntrue = 0;
+  while (H.it < maxit) {
     if ((rc = fx_symbol<C>(R, t, true))) return rc;
-    if ((rc = fx_row<C, C, FX_FUSED>(R, t, x, y, bu, b2, alpha, 1, R.part() + (it % kFxRows) * R.L.pitch,
-                                     nullptr)))
-      return rc;
-    ++it;
-    if (it - flushed == kFxRows && (rc = flush())) return rc;
+    if ((rc = fx_row<C, C, FX_FUSED>(R, t, x, y, bu, b2, alpha, 1, H.row(), nullptr))) return rc;
+    if ((rc = H.step())) return rc;
+    const int it = H.it;
     const bool chk = it % check_every == 0 || it == maxit;
-    if (chk || it - pulled >= kFxHist / 2) {
-      if ((rc = flush()) || (rc = pull())) return rc;
-      if (status == USP_ERR_NAN || status == USP_DIVERGED) break;
+    if (chk || it - H.pulled >= kFxHist / 2) {
+      if ((rc = H.sync())) return rc;
+      if (H.status == USP_ERR_NAN || H.status == USP_DIVERGED) break;
     }
     if (chk) {
       double rho;
@@ -322,24 +359,96 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
         hist_true[2 * ntrue + 1] = rho;
       }
       ++ntrue;
-      if (!(rho == rho)) { status = USP_ERR_NAN; break; }
-      if (rho < tol) { status = USP_OK; break; }
+      if (!(rho == rho)) { H.status = USP_ERR_NAN; break; }
+      if (rho < tol) { H.status = USP_OK; break; }
     }
   }
-  if ((rc = flush()) || (rc = pull())) return rc;
-  if (iters_out) *iters_out = it;
+  if ((rc = H.sync())) return rc;
+  if (iters_out) *iters_out = H.it;
   if (n_true_out) *n_true_out = ntrue;
-  if (status < 0) return fail(status, "non-finite values in the iteration");
-  return status;
+  if (H.status < 0) return fail(H.status, "non-finite values in the iteration");
+  return H.status;
 }
 
-int fx_begin(const usp_flux_symbol* sym, int dtype, void* ws, size_t ws_bytes, void* stream, FxRun* R) {
+// Refined solve (complex128 x): FP64 residual r = y - A x every cycle, then up
+// to k complex64 iterations of Algorithm 1 on A d = r from d = 0, added to x by
+// the next residual's first pass.  As in the main path, the final cycle is cut
+// to the count that the latest rate of ||Delta|| predicts for reaching tol
+// when that is under half a cycle.
+int fx_solve_refined(const FxRun& R, const double2* bu, const double2* b2, const double2* y, double2* x,
+                     int x_is_guess, double alpha, double tol, int maxit, int k, int* iters_out, double* hist_pre,
+                     int hist_pre_cap, double* hist_true, int hist_true_cap, int* n_true_out) {
+  int rc;
+  const long nb2 = (long)R.d * R.d * R.N;
+  float2 *bu32 = R.f32(R.L.bu32), *b232 = R.f32(R.L.b232), *r32 = R.f32(R.L.r32), *d32 = R.f32(R.L.d32);
+  float2* t = R.t<float2>();
+  hipLaunchKernelGGL(k_fx_to32<0>, dim3(1024), dim3(256), 0, R.st, bu, bu32, R.N);
+  hipLaunchKernelGGL(k_fx_to32<0>, dim3(1024), dim3(256), 0, R.st, b2, b232, nb2);
+  LAUNCHCHK("k_fx_to32");
+  if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * (R.d + 1) * R.N, R.st));
+  FxHist H{R, hist_pre, hist_pre_cap};
+  int ntrue = 0;
+  bool judge = x_is_guess == 2;
+  const float2* dcor = nullptr;
+  std::vector<double> rhos;
+  while (true) {
+    double rho;
+    if ((rc = fx_residual<double2>(R, bu, b2, y, x, &rho, dcor, r32))) return rc;
+    dcor = nullptr;
+    if ((rc = H.sync())) return rc;
+    if (hist_true && ntrue < hist_true_cap) {
+      hist_true[2 * ntrue] = H.it;
+      hist_true[2 * ntrue + 1] = rho;
+    }
+    ++ntrue;
+    if (judge) {
+      // a guess whose residual is not below ||y|| is discarded: restart from x = 0
+      judge = false;
+      if (!(rho < 1.0)) {
+        HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * (R.d + 1) * R.N, R.st));
+        continue;
+      }
+    }
+    if (!(rho == rho) || H.status == USP_ERR_NAN) { H.status = USP_ERR_NAN; break; }
+    if (rho < tol) { H.status = USP_OK; break; }
+    if (H.status == USP_DIVERGED) break;
+    // no 1% improvement of the FP64 residual over 8 checks
+    rhos.push_back(rho);
+    if (rhos.size() > 8 && rho > 0.99 * rhos[rhos.size() - 9]) { H.status = USP_STAGNATED; break; }
+    if (H.it >= maxit) break;
+    int m = std::min(k, maxit - H.it);
+    if (H.ntail >= 11) {
+      const double a = H.tail[(H.ntail - 1) % 16], b = H.tail[(H.ntail - 11) % 16];
+      if (a > 0.0 && a < b) {
+        const double lrate = 0.05 * std::log(a / b);   // log of the per-iteration factor of ||Delta||
+        const double need = std::log(tol / rho) / lrate;
+        if (need < 0.5 * m) m = std::max(1, (int)std::ceil(1.05 * need) + 1);
+      }
+    }
+    HIPCHK(hipMemsetAsync(d32, 0, sizeof(float2) * (R.d + 1) * R.N, R.st));
+    if ((rc = fx_row<float2, float2, FX_FIRST>(R, t, d32, r32, bu32, b232, 0.0, 0, nullptr, nullptr))) return rc;
+    for (int j = 0; j < m; ++j) {
+      if ((rc = fx_symbol<float2>(R, t, true))) return rc;
+      if ((rc = fx_row<float2, float2, FX_FUSED>(R, t, d32, r32, bu32, b232, alpha, 1, H.row(), nullptr))) return rc;
+      if ((rc = H.step())) return rc;
+    }
+    dcor = d32;
+  }
+  HIPCHK(hipStreamSynchronize(R.st));
+  if (iters_out) *iters_out = H.it;
+  if (n_true_out) *n_true_out = ntrue;
+  if (H.status < 0) return fail(H.status, "non-finite values in the iteration");
+  return H.status;
+}
+
+int fx_begin(const usp_flux_symbol* sym, int dtype, void* ws, size_t ws_bytes, void* stream, FxRun* R,
+             bool refined = false) {
   int rc = fx_check(sym, dtype);
   if (rc) return rc;
   R->sym = sym;
   R->d = sym->ndim;
   if ((rc = fx_sym(sym, &R->fs))) return rc;
-  R->L = fx_layout(sym, dtype);
+  R->L = refined ? fx_layout(sym, USP_C64, true) : fx_layout(sym, dtype);
   if (!ws || ws_bytes < R->L.total)
     return fail(USP_ERR_WORKSPACE, "flux workspace too small: need " + std::to_string(R->L.total) + " bytes");
   if (((uintptr_t)ws) & 255) return fail(USP_ERR_WORKSPACE, "workspace must be 256-byte aligned");
@@ -378,6 +487,29 @@ int usp_flux_solve(const usp_flux_symbol* sym, int dtype, const void* bu_dev, co
   return fx_solve<double2>(R, (const double2*)bu_dev, (const double2*)b2_dev, (const double2*)y_dev, (double2*)x_dev,
                            x_is_guess, alpha, tol, maxit, check_every, iters_out, hist_pre, hist_pre_cap, hist_true,
                            hist_true_cap, n_true_out);
+}
+
+int usp_flux_refined_workspace_bytes(const usp_flux_symbol* sym, size_t* bytes) {
+  int rc = fx_check(sym, USP_C128);
+  if (rc) return rc;
+  if (!bytes) return fail(USP_ERR_INVALID, "bytes is NULL");
+  *bytes = fx_layout(sym, USP_C64, true).total;
+  return 0;
+}
+
+int usp_flux_solve_refined(const usp_flux_symbol* sym, const void* bu_dev, const void* b2_dev, const void* y_dev,
+                           void* x_dev, int x_is_guess, double alpha, double tol, int maxit, int refine_every,
+                           void* ws_dev, size_t ws_bytes, void* stream, int* iters_out, double* hist_pre,
+                           int hist_pre_cap, double* hist_true, int hist_true_cap, int* n_true_out) {
+  if (!bu_dev || !b2_dev || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  if (!(alpha > 0.0) || maxit < 0 || refine_every < 1)
+    return fail(USP_ERR_INVALID, "alpha > 0, maxit >= 0, refine_every >= 1");
+  FxRun R;
+  int rc = fx_begin(sym, USP_C128, ws_dev, ws_bytes, stream, &R, true);
+  if (rc) return rc;
+  return fx_solve_refined(R, (const double2*)bu_dev, (const double2*)b2_dev, (const double2*)y_dev,
+                          (double2*)x_dev, x_is_guess, alpha, tol, maxit, refine_every, iters_out, hist_pre,
+                          hist_pre_cap, hist_true, hist_true_cap, n_true_out);
 }
 
 int usp_flux_residual(const usp_flux_symbol* sym, int dtype, const void* bu_dev, const void* b2_dev,

@@ -252,16 +252,18 @@ k_fx_col(C* __restrict__ data, const C* __restrict__ tw, FluxSym fs) {
 //   FX_FIRST  t = B x + y (x = 0 unless has_x), forward FFT -> spec
 //   FX_FUSED  spec -> inverse FFT = u; Delta = B (u - x); x += alpha Delta;
 //             ||Delta||^2 block partial -> row0; t = B x + y; forward FFT -> spec
-//   FX_RFWD   spec = forward FFT of x
+//   FX_RFWD   spec = forward FFT of x; with dcor, x += dcor first (stored)
 //   FX_RINV   spec (= L x) -> inverse FFT; r = y - L x - x + B x;
-//             ||r||^2 -> row0, ||y||^2 -> row1 (block partials)
+//             ||r||^2 -> row0, ||y||^2 -> row1 (block partials); with r32,
+//             r rounded to complex64 is stored there
 // Rows at or beyond nrows compute on zeros and store nothing, so every thread
 // takes every barrier.
 template <class Cc, class Cx, int N, int D, int MODE>
 __global__ void __launch_bounds__((D + 1) * FxRow<N>::G)
 k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, const Cx* __restrict__ bu,
          const Cx* __restrict__ b2, const Cc* __restrict__ tw, double alpha, long nrows, int has_x,
-         double* __restrict__ row0, double* __restrict__ row1) {
+         double* __restrict__ row0, double* __restrict__ row1, const float2* __restrict__ dcor,
+         float2* __restrict__ r32) {
   using Rr = typename real_of<Cc>::type;
   using FR = FxRow<N>;
   using P = typename FR::PL::P;
@@ -337,6 +339,13 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
   } else if (MODE == FX_RFWD) {
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = ld(x, e);
+    if (dcor && act) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        a[e] = cadd(a[e], cvt<Cc>(dcor[base + tt + T * e]));
+        x[base + tt + T * e] = cvt<Cx>(a[e]);
+      }
+    }
     FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, BlockSync{});
     if (act) {
 #pragma unroll
@@ -389,6 +398,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
     for (int e = 0; e < E; ++e) {
       const Cc yv = ld(y, e);
       const Cc res = cadd(csub(csub(yv, a[e]), xv[e]), bapply(e, xv[e], fl));
+      if (r32 && act) r32[base + tt + T * e] = cvt<float2>(res);
       rr += cabs2(res);
       yy += cabs2(yv);
     }
@@ -399,6 +409,13 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
       row1[blockIdx.x] = yy;
     }
   }
+}
+
+// complex128 -> complex64 copy (grid-stride)
+template <int U = 0>
+__global__ void __launch_bounds__(256) k_fx_to32(const double2* __restrict__ in, float2* __restrict__ out, long n) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = make_float2((float)in[i].x, (float)in[i].y);
 }
 
 // block i adds row (first + i) % ring of `part` (ncols partials each, pitch

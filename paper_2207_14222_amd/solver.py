@@ -411,17 +411,24 @@ class FluxOperator:
     3-D.  Fields are (1 + d,) + grid tensors: [u; Jx; Jy (; Jz)] of the
     canonical system."""
 
-    def __init__(self, mu, D, source, h, vnorm: float = 0.95, dtype=torch.complex128, device="cuda"):
+    def __init__(self, mu, D, source, h, vnorm: float = 0.95, dtype=torch.complex128, device="cuda",
+                 refine: bool = False):
+        if refine and dtype != torch.complex128:
+            raise ValueError("refine=True needs complex128 fields")
         self.sym, bu, b2, y = canonical_flux_host(mu, D, source, h, vnorm)
         self.device = torch.device(device)
         self.dtype = dtype
+        self.refine = refine
         self.dt = L.USP_C64 if dtype == torch.complex64 else L.USP_C128
         T = lambda z: torch.from_numpy(z).to(device=self.device, dtype=dtype)
         self.bu, self.b2, self.y = T(bu), T(b2), T(y)
         self.device = self.y.device          # "cuda" resolved to "cuda:<index>"
         self.shape = tuple(y.shape)
         nb = ct.c_size_t()
-        L.check(L.lib().usp_flux_workspace_bytes(ct.byref(self.sym), self.dt, ct.byref(nb)))
+        if refine:
+            L.check(L.lib().usp_flux_refined_workspace_bytes(ct.byref(self.sym), ct.byref(nb)))
+        else:
+            L.check(L.lib().usp_flux_workspace_bytes(ct.byref(self.sym), self.dt, ct.byref(nb)))
         self.ws_bytes = nb.value
         self.workspace = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
 
@@ -438,19 +445,29 @@ class FluxOperator:
             raise ValueError(f"expected a contiguous {self.dtype} tensor of shape {self.shape} on {self.device}")
         return t
 
-    def solve(self, y=None, x=None, alpha=1.0, tol=1e-6, maxit=10000, check_every=20) -> SolveResult:
+    def solve(self, y=None, x=None, alpha=1.0, tol=1e-6, maxit=10000, check_every=20, judge_guess=False) -> SolveResult:
+        """Algorithm 1; with refine=True, check_every is the refinement interval
+        (complex64 inner iterations, FP64 residual and update every cycle) and
+        judge_guess discards a guess whose residual is not below ||y||."""
         y = self.y if y is None else self._field(y)
         guess = x is not None
         x = self._field(x) if guess else torch.empty_like(y)
         hp = np.zeros(max(maxit, 1))
-        ntc = maxit // check_every + 2
+        ntc = maxit + 2 if self.refine else maxit // check_every + 2
         ht = np.zeros(2 * ntc)
         it, nt = ct.c_int(), ct.c_int()
-        rc = L.check(L.lib().usp_flux_solve(ct.byref(self.sym), self.dt, _ptr(self.bu), _ptr(self.b2), _ptr(y),
-                                            _ptr(x), int(guess), float(alpha), float(tol), int(maxit),
-                                            int(check_every), _ptr(self.workspace), self.ws_bytes,
-                                            _stream_ptr(self.device), ct.byref(it), _dp(hp), maxit, _dp(ht), ntc,
-                                            ct.byref(nt)))
+        g = (2 if judge_guess else 1) if guess else 0
+        if self.refine:
+            rc = L.check(L.lib().usp_flux_solve_refined(
+                ct.byref(self.sym), _ptr(self.bu), _ptr(self.b2), _ptr(y), _ptr(x), g, float(alpha), float(tol),
+                int(maxit), int(check_every), _ptr(self.workspace), self.ws_bytes, _stream_ptr(self.device),
+                ct.byref(it), _dp(hp), maxit, _dp(ht), ntc, ct.byref(nt)))
+        else:
+            rc = L.check(L.lib().usp_flux_solve(ct.byref(self.sym), self.dt, _ptr(self.bu), _ptr(self.b2), _ptr(y),
+                                                _ptr(x), g, float(alpha), float(tol), int(maxit),
+                                                int(check_every), _ptr(self.workspace), self.ws_bytes,
+                                                _stream_ptr(self.device), ct.byref(it), _dp(hp), maxit, _dp(ht), ntc,
+                                                ct.byref(nt)))
         m = min(nt.value, ntc)
         return SolveResult(x=x, iterations=it.value, status=rc, hist_pre=hp[:min(it.value, maxit)].copy(),
                            hist_true=ht[:2 * m].reshape(m, 2).copy())

@@ -13,7 +13,11 @@ FP64 oracle:
   tests/golden/make_flux_golden.py) with ||Delta|| non-increasing;
 * 3-D (four components): K iterates on random tensor media over grids whose
   sides differ (every axis length from 8 to 64 in each position), the FP64
-  residual, and the solve against dense LU on an 8^3 grid."""
+  residual, and the solve against dense LU on an 8^3 grid;
+* the refined solve (complex64 inner iterations, FP64 refinement): three
+  cycles against the oracle's FP64 refinement (2-D and 3-D, 3e-5), FP64
+  accuracy against dense LU, the iteration count at 256 x 256 against the
+  oracle checkpoint, and the judged initial guess (discarded or kept)."""
 import json
 import os
 
@@ -176,3 +180,75 @@ def test_3d_solution_matches_dense_lu():
     assert rel(gop.physical(r.x).cpu().numpy(), op.physical(xs)) < 1e-8
     d = np.sqrt(r.hist_pre)
     assert np.all(np.diff(d) <= 1e-12 * d[0])
+
+
+# ---- mixed precision: complex64 inner iterations, FP64 refinement -----------
+
+def _refined(p):
+    from paper_2207_14222_amd import solver
+    cp = F.canonical_flux(p.mu, p.D, p.source, p.h)
+    return cp, F.FluxOperator(cp), solver.FluxOperator(p.mu, p.D, p.source, p.h, refine=True)
+
+
+@pytest.mark.parametrize("name", ["ring64", "rand32x128", "cube16x32x8"])
+def test_refined_cycles_match_oracle(name):
+    """Three cycles of 20 inner iterations (no early stop): x after the last
+    FP64 update and every cycle's FP64 residual against the oracle's FP64
+    refinement (complex64 inner arithmetic: 3e-5)."""
+    _need_gpu()
+    print(f"[gpu-case] flux refined cycles {name}", flush=True)
+    p = media.diffusion_tensor_random3(shape=(16, 32, 8), seed=3) if name == "cube16x32x8" else _medium(name)
+    cp, op, gop = _refined(p)
+    ro = R.solve_refined(op, cp.y, 0.9, -1.0, 60, inner=20)
+    r = gop.solve(alpha=0.9, tol=-1.0, maxit=60, check_every=20)
+    assert r.status_name == "maxit" and r.iterations == 60
+    assert rel(r.x.cpu().numpy(), ro.x) < 3e-5
+    ht = np.array(ro.hist_true)
+    assert r.hist_true.shape == ht.shape == (4, 2)
+    np.testing.assert_array_equal(r.hist_true[:, 0], ht[:, 0])
+    np.testing.assert_allclose(r.hist_true[:, 1], ht[:, 1], rtol=1e-3)
+    np.testing.assert_allclose(np.sqrt(r.hist_pre), ro.hist_pre, rtol=1e-3)
+    # the library's FP64 residual of the returned x agrees with the last check
+    assert abs(gop.residual(r.x) - r.hist_true[-1, 1]) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["ring16", "cube8"])
+def test_refined_reaches_dense_lu(name):
+    """The refinement reaches FP64 accuracy from complex64 iterations: 1e-11
+    relative residual, and the dense-LU solution to 1e-8."""
+    _need_gpu()
+    print(f"[gpu-case] flux refined dense {name}", flush=True)
+    p = media.diffusion_tensor_random3(shape=(8, 8, 8), seed=21) if name == "cube8" else _medium(name)
+    cp, op, gop = _refined(p)
+    xs = np.linalg.solve(op.dense(op.apply_A), cp.y.ravel()).reshape(op.shape)
+    r = gop.solve(alpha=1.0, tol=1e-11, maxit=50000, check_every=50)
+    assert r.converged, r.status_name
+    assert r.hist_true[-1, 1] < 1e-11
+    assert rel(r.x.cpu().numpy(), xs) < 1e-8
+
+
+def test_refined_ring256_iterations_and_guess():
+    """At 256 x 256 the refined solve to the oracle checkpoint's tolerance takes
+    no more iterations than the complex128 solve plus the final cycle's
+    prediction margin; a guess whose residual is above ||y|| is discarded
+    (restart from 0, same result), a good one is kept."""
+    _need_gpu()
+    print("[gpu-case] flux refined ring256", flush=True)
+    g = json.load(open(GOLDEN))
+    run = min(g["runs"], key=lambda q: q["tol"])
+    p = _medium("ring256")
+    cp, op, gop = _refined(p)
+    r = gop.solve(alpha=run["alpha"], tol=run["tol"], maxit=20000, check_every=100)
+    assert r.converged, r.status_name
+    assert r.iterations <= run["iterations"] + max(5, run["iterations"] // 20)
+    assert gop.residual(r.x) < run["tol"]
+    bad = torch.full(gop.shape, 1e3 + 0j, dtype=torch.complex128, device="cuda")
+    rb = gop.solve(x=bad, alpha=run["alpha"], tol=run["tol"], maxit=20000, check_every=100, judge_guess=True)
+    assert rb.hist_true[0, 1] >= 1.0 and rb.hist_true[1, 0] == 0 and abs(rb.hist_true[1, 1] - 1.0) < 1e-12
+    assert rb.converged and rb.iterations == r.iterations
+    assert rel(rb.x.cpu().numpy(), r.x.cpu().numpy()) < 1e-12
+    xo, _ = R.iterate(op, cp.y, run["alpha"], 200)
+    rg = gop.solve(x=torch.from_numpy(xo).to("cuda"), alpha=run["alpha"], tol=run["tol"], maxit=20000,
+                   check_every=100, judge_guess=True)
+    assert rg.converged and rg.hist_true[0, 1] < 1.0
+    assert rg.iterations < r.iterations
