@@ -459,7 +459,7 @@ def main():
     ap.add_argument("--shape", default="256,256,256")
     ap.add_argument("--alpha", type=float, default=0.9, help="step size of the headline and comparison solves")
     ap.add_argument("--batch-alpha", type=float, default=0.9, help="step size of the batched 2-D problems")
-    ap.add_argument("--batch-refine-every", type=int, default=60,
+    ap.add_argument("--batch-refine-every", type=int, default=150,
                     help="refinement interval of the batched schedule and of its one-at-a-time refined comparison")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--refine-every", type=int, default=100,

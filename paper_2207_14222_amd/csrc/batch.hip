@@ -165,15 +165,16 @@ int launch_inner_cycle(hipStream_t st, const BatchProblem* dtab, GState* dst, do
                        const GTask* xt, int nx, const GTask* s64, int ns64, const GTask* s128, int ns128,
                        const int* nslots, int nprob, int k) {
   // complex64 inner iterations on A d = r from d = 0
-  hipLaunchKernelGGL((k_gx<1, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch);
+  // (problems whose cycle budget is below k skip the remaining launches)
+  hipLaunchKernelGGL((k_gx<1, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL((k_gs<0>), dim3(ns64), dim3(kGS64), 0, st, s64, dtab, dst);
-    hipLaunchKernelGGL((k_gx<2, FL>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch);
+    hipLaunchKernelGGL((k_gs<0>), dim3(ns64), dim3(kGS64), 0, st, s64, dtab, dst, j);
+    hipLaunchKernelGGL((k_gx<2, FL>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, j);
   }
   // FP64 residual of x + d (x += d) and the per-problem decision
-  hipLaunchKernelGGL((k_gx<5, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch);
-  hipLaunchKernelGGL((k_gs<1>), dim3(ns128), dim3(kGS128), 0, st, s128, dtab, dst);
-  hipLaunchKernelGGL((k_gx<4, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch);
+  hipLaunchKernelGGL((k_gx<5, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
+  hipLaunchKernelGGL((k_gs<1>), dim3(ns128), dim3(kGS128), 0, st, s128, dtab, dst, 0);
+  hipLaunchKernelGGL((k_gx<4, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
   hipLaunchKernelGGL((k_gfinal<false>), dim3(nprob), dim3(256), 0, st, dtab, dst, part, pitch, nslots, k);
   return 0;
 }
@@ -227,11 +228,11 @@ int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w
   HIPCHK(hipEventRecord(e0, st));
   if (cs != st) HIPCHK(hipStreamWaitEvent(cs, e0, 0));
   // init (B32, x = 0, |y|^2), then the first FP64 residual and decision
-  hipLaunchKernelGGL((k_gx<0, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch);
-  hipLaunchKernelGGL((k_gfinal<true>), dim3(nprob), dim3(256), 0, cs, dtab, dst, part, L.pitch, dns, 0);
-  hipLaunchKernelGGL((k_gx<3, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch);
-  hipLaunchKernelGGL((k_gs<1>), dim3(T.s128.size()), dim3(kGS128), 0, cs, ds128, dtab, dst);
-  hipLaunchKernelGGL((k_gx<4, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch);
+  hipLaunchKernelGGL((k_gx<0, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch, 0);
+  hipLaunchKernelGGL((k_gfinal<true>), dim3(nprob), dim3(256), 0, cs, dtab, dst, part, L.pitch, dns, k);
+  hipLaunchKernelGGL((k_gx<3, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch, 0);
+  hipLaunchKernelGGL((k_gs<1>), dim3(T.s128.size()), dim3(kGS128), 0, cs, ds128, dtab, dst, 0);
+  hipLaunchKernelGGL((k_gx<4, 0>), dim3(T.xt.size()), dim3(kGX), 0, cs, dxt, dtab, dst, part, L.pitch, 0);
   hipLaunchKernelGGL((k_gfinal<false>), dim3(nprob), dim3(256), 0, cs, dtab, dst, part, L.pitch, dns, 0);
   LAUNCHCHK("grouped init");
   std::vector<GState> hs(nprob);

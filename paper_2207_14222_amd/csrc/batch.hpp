@@ -99,8 +99,8 @@ __device__ __noinline__ void batch_solve(const BatchProblem& P, BatchResult* res
   SymArgs si = sr;  // iteration: 1/(NN (l(p) + 1))
   si.c0r += 1.0;
 
-  int it = 0, status = 1, since_best = 0;
-  double rho = 0.0, best = 1e300;
+  int it = 0, status = 1, since_best = 0, ran = 0;
+  double rho = 0.0, best = 1e300, rho_prev = 0.0;
   const float2* dcorr = nullptr;
   for (;;) {
     // FP64 residual r = y - A (x + d); x += d; r32 = complex64(r)
@@ -127,8 +127,18 @@ __device__ __noinline__ void batch_solve(const BatchProblem& P, BatchResult* res
       break;
     }
     if (it >= P.maxit) { status = 1; break; }
-    // complex64 inner iterations on A d = r from d = 0
-    const int m = min(P.k, P.maxit - it);
+    // complex64 inner iterations on A d = r from d = 0: k, or fewer when the
+    // residual's rate over the last cycle predicts the crossing of tol within
+    // half a cycle (the rule of the grouped schedule)
+    int nb = P.k;
+    if (ran > 0 && rho > 0.0 && rho < rho_prev) {
+      const double lrate = log(rho / rho_prev) / ran;
+      const double need = log(P.tol / rho) / lrate;
+      if (need < 0.5 * nb) nb = max(1, (int)ceil(1.05 * need) + 1);
+    }
+    const int m = max(1, min(nb, P.maxit - it));
+    rho_prev = rho;
+    ran = m;
     for (long i = tid; i < NN; i += kBatchThreads) P.d32[i] = mk<float2>(0.0, 0.0);
     for (int l0 = 0; l0 < N; l0 += L64)
       xpass_body<float2, float2, N, X_FIRST, 0, L64>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr, twf,

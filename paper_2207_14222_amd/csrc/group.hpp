@@ -27,6 +27,9 @@ struct GState {
   double rho;
   double ynorm2;
   unsigned long long t_start, t_done;
+  double rho_prev; // FP64 residual before the last cycle
+  int budget;      // inner iterations of the next cycle (at most kmax)
+  int kmax;        // refinement interval k
 };
 
 constexpr int kGX = 256;   // threads of the contiguous-axis group kernels
@@ -36,6 +39,9 @@ constexpr int kGS128 = 256;
 template <int N> constexpr int g_lpb() { return kGX / (N / PassPlan<N>::E); }
 template <int N> constexpr int g_w64() { return cmin(cmin(kGS64 / (N / PassPlan<N>::E), 16), N); }
 template <int N> constexpr int g_w128() { return cmin(cmin(kGS128 / (N / PassPlan<N>::E), 8), N); }
+// complex64 t of the 1024^2 problems is kept in column tiles of g_w64 (the
+// column pass reads 64 KB blocks instead of 64-byte row segments)
+template <int N> constexpr int g_tile() { return N == 1024 ? g_w64<N>() : 0; }
 
 template <class C> __device__ __forceinline__ void copy_tw(C* tws, const C* tw, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) tws[i] = tw[i];
@@ -43,11 +49,12 @@ template <class C> __device__ __forceinline__ void copy_tw(C* tws, const C* tw, 
 }
 
 // GMODE: 0 init (B32, x = 0, |y|^2), 1 FIRST, 2 FUSED, 3 RFWD (first residual),
-// 4 RINV, 5 RFWD after inner iterations (x += d first)
+// 4 RINV, 5 RFWD after inner iterations (x += d first).  j: index of a FUSED
+// launch within the cycle; problems whose cycle budget is spent skip it.
 template <int GMODE, int FL>
 __global__ void __launch_bounds__(kGX)
 k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, const GState* __restrict__ st,
-     double* __restrict__ part, long pitch) {
+     double* __restrict__ part, long pitch, int j) {
   constexpr bool F64 = (GMODE == 3 || GMODE == 4 || GMODE == 5);
   using C = typename std::conditional<F64, double2, float2>::type;
   __shared__ C lds[kGX * 17];
@@ -55,6 +62,7 @@ k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
   __shared__ double scratch[64];
   const GTask tk = tasks[blockIdx.x];
   if (GMODE != 0 && st[tk.p].done) return;  // whole block; the state is not yet set during init
+  if (GMODE == 2 && j >= st[tk.p].budget) return;
   const BatchProblem P = probs[tk.p];
   double acc = 0.0;
   auto run = [&](auto NC) {
@@ -84,11 +92,11 @@ k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
     } else {
       copy_tw(reinterpret_cast<float2*>(tws), P.twf, N);
       if (GMODE == 1) {
-        xpass_body<float2, float2, N, X_FIRST, 0, LPB>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
+        xpass_body<float2, float2, N, X_FIRST, 0, LPB, g_tile<N>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
                                                        reinterpret_cast<float2*>(tws), reinterpret_cast<float2*>(lds),
                                                        0.0, tk.start, N, 2);
       } else {
-        xpass_body<float2, float2, N, X_FUSED, FL, LPB>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
+        xpass_body<float2, float2, N, X_FUSED, FL, LPB, g_tile<N>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
                                                         reinterpret_cast<float2*>(tws),
                                                         reinterpret_cast<float2*>(lds), P.alpha, tk.start, N, 1);
       }
@@ -112,10 +120,10 @@ k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
 }
 
 // strided pass along axis 0 of every task's problem: SYM (complex64,
-// 1/(N (l + 1))) or SYMA (complex128, l(p)/N)
+// 1/(N (l + 1))) or SYMA (complex128, l(p)/N); j as in k_gx for SYM
 template <int GMODE>
 __global__ void __launch_bounds__(GMODE == 0 ? kGS64 : kGS128)
-k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, const GState* __restrict__ st) {
+k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, const GState* __restrict__ st, int j) {
   constexpr bool F64 = (GMODE == 1);
   using C = typename std::conditional<F64, double2, float2>::type;
   constexpr int LDSN = F64 ? 1024 * 5 : 1024 * 9;
@@ -126,6 +134,7 @@ k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
   const int nb = gridDim.x, nb8 = nb - nb % 8, bb = blockIdx.x;
   const GTask tk = tasks[bb < nb8 ? (bb % 8) * (nb8 / 8) + bb / 8 : bb];
   if (st[tk.p].done) return;
+  if (GMODE == 0 && j >= st[tk.p].budget) return;
   const BatchProblem P = probs[tk.p];
   SymArgs sym;
   sym.sa = P.sa;
@@ -148,8 +157,8 @@ k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
     } else {
       constexpr int W = g_w64<N>();
       static_assert(N * (W + 1) <= LDSN, "LDS tile");
-      spass_body<float2, N, W, S_SYM>(P.t, P.twf, reinterpret_cast<float2*>(tws), reinterpret_cast<float2*>(lds),
-                                      N, sym, tk.start, 0);
+      spass_body<float2, N, W, S_SYM, (g_tile<N>() > 0)>(P.t, P.twf, reinterpret_cast<float2*>(tws),
+                                                         reinterpret_cast<float2*>(lds), N, sym, tk.start, 0);
     }
   };
   switch (P.n) {
@@ -165,9 +174,13 @@ k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
   }
 }
 
-// One block per problem.  INIT: |y|^2 and the state; otherwise: the residual
-// decision after `m` more inner iterations (converged / stagnated / maxit /
-// non-finite), with the problem's finishing timestamp.
+// One block per problem.  INIT: |y|^2 and the state, m = the refinement
+// interval k.  Otherwise: the residual decision after the cycle that just ran
+// (m > 0; m = 0 for the check of the initial x), converged / stagnated / maxit
+// / non-finite, with the problem's finishing timestamp, and the next cycle's
+// budget: k, or fewer when the residual's rate over the last cycle predicts
+// the crossing of tol within half a cycle (the margin of the single-problem
+// solve).
 template <bool INIT>
 __global__ void __launch_bounds__(256)
 k_gfinal(const BatchProblem* __restrict__ probs, GState* __restrict__ st, const double* __restrict__ part, long pitch,
@@ -190,10 +203,14 @@ k_gfinal(const BatchProblem* __restrict__ probs, GState* __restrict__ st, const 
     g.ynorm2 = s;
     g.t_start = wall_clock64();
     g.t_done = g.t_start;
+    g.rho_prev = 1.0;
+    g.kmax = m > 0 ? m : 1;
+    g.budget = g.kmax;
     st[p] = g;
     return;
   }
-  g.iterations += m;
+  const int ran = m > 0 ? g.budget : 0;
+  g.iterations += ran;
   const double rho = sqrt(s / g.ynorm2);
   g.rho = rho;
   int fin = -100;
@@ -212,7 +229,16 @@ k_gfinal(const BatchProblem* __restrict__ probs, GState* __restrict__ st, const 
     g.done = 1;
     g.status = fin;
     g.t_done = wall_clock64();
+  } else {
+    int nb = g.kmax;
+    if (ran > 0 && rho > 0.0 && rho < g.rho_prev) {
+      const double lrate = log(rho / g.rho_prev) / ran;   // log of the per-iteration factor
+      const double need = log(probs[p].tol / rho) / lrate;
+      if (need < 0.5 * nb) nb = max(1, (int)ceil(1.05 * need) + 1);
+    }
+    g.budget = max(1, min(nb, probs[p].maxit - g.iterations));
   }
+  g.rho_prev = rho;
   st[p] = g;
 }
 

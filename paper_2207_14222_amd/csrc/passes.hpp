@@ -101,7 +101,10 @@ template <int N, class P> __device__ __forceinline__ void idle_fft_syncs() {
 // partial sum of |Delta|^2 (X_FUSED) or |r|^2 (X_RINV).
 // FL (fused pass only): bit 0 = load x, B, y before the inverse FFT;
 // bit 1 = stream x, B, y (non-temporal loads / store).
-template <class Cc, class Cx, int N, int MODE, int FL, int LPB>
+// TL (X_FIRST / X_FUSED): 0 = t row-major like x; TL > 0 = t in column tiles
+// of width TL, element (line, pos) at ((pos / TL) nlines + line) TL + pos % TL,
+// so that the strided pass reads each tile as one contiguous block.
+template <class Cc, class Cx, int N, int MODE, int FL, int LPB, int TL = 0>
 __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y,
                                              const Cx* __restrict__ B, const float2* __restrict__ d,
                                              float2* __restrict__ r32, const Cc* tws, Cc* lds, double alpha,
@@ -128,6 +131,9 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
   LdsRow<Cc> row{lds + li * PADN};
   Cc v[E];
   double acc = 0.0;
+  auto tix = [&](int pos) -> long {
+    return TL ? ((long)(pos / TL) * nlines + line) * TL + pos % TL : base + pos;
+  };
 
   if (MODE == X_FIRST) {
 #pragma unroll
@@ -144,7 +150,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
     FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
+      for (int e = 0; e < E; ++e) t[tix(tt + T * e)] = v[e];
     }
     return 0.0;
   }
@@ -157,7 +163,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const long p = base + tt + T * e;
-      v[e] = active ? t[p] : mk<Cc>(0.0, 0.0);
+      v[e] = active ? t[tix(tt + T * e)] : mk<Cc>(0.0, 0.0);
       if (PF) {
         xx[e] = active ? cvt<Cc>(ld<NT>(x + p)) : mk<Cc>(0.0, 0.0);
         bb[e] = active ? cvt<Cc>(ld<NT>(B + p)) : mk<Cc>(0.0, 0.0);
@@ -186,7 +192,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
     FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
     if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
+      for (int e = 0; e < E; ++e) t[tix(tt + T * e)] = v[e];
     }
     return acc;
   }
@@ -267,8 +273,10 @@ template <class C> constexpr bool s_width_ok(int N, int W, int E) {
 // Body of the strided pass for columns col0 .. col0 + W - 1 of batch b.
 // Threads >= W*T only join the barriers (whole waves, or no barriers at all
 // for single-stage plans).  If tw_g is non-NULL the twiddles are copied into
-// tws after the column loads are issued.
-template <class C, int N, int W, int MODE>
+// tws after the column loads are issued.  TILED: data in column tiles of
+// width W (the TL layout of xpass_body with N lines, b = 0): the tile is the
+// contiguous block of N W values at col0 N, and S is ignored.
+template <class C, int N, int W, int MODE, bool TILED = false>
 __device__ __forceinline__ void spass_body(C* __restrict__ data, const C* __restrict__ tw_g, C* tws, C* lds, long S,
                                            const SymArgs& sym, long col0, long b) {
   using Rr = typename real_of<C>::type;
@@ -283,7 +291,8 @@ __device__ __forceinline__ void spass_body(C* __restrict__ data, const C* __rest
   }
   const int c = tid % W, tt = tid / W;
   const long col = col0 + c;
-  const long base = b * N * S + col;
+  if (TILED) S = W;
+  const long base = TILED ? col0 * N + c : b * N * S + col;
   LdsCol<C, W> line{lds + c};
   C v[E];
 #pragma unroll
@@ -300,14 +309,18 @@ __device__ __forceinline__ void spass_body(C* __restrict__ data, const C* __rest
     const int cl = (int)col;
     const Rr qc = (Rr)sym.sm * fsq<Rr>(cl >> sym.log2_n2, sym.n1) + (Rr)sym.sx * fsq<Rr>(cl & (n2 - 1), n2);
     const Rr sa = (Rr)sym.sa;
+    // the 1/Ntotal of the inverse transform is a power of two, so it is folded
+    // exactly into the coefficients: scale / m = 1 / (m / scale), m scale
+    const double k = MODE == S_SYM ? 1.0 / sym.scale : sym.scale;
+    const Rr c0r = (Rr)(sym.c0r * k), c0i = (Rr)(sym.c0i * k), c2r = (Rr)(sym.c2r * k), c2i = (Rr)(sym.c2i * k);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const Rr p2 = sa * fsq<Rr>(tt + T * e, N) + qc;
       C m;
-      m.x = (Rr)sym.c0r + (Rr)sym.c2r * p2;
-      m.y = (Rr)sym.c0i + (Rr)sym.c2i * p2;
+      m.x = c0r + c2r * p2;
+      m.y = c0i + c2i * p2;
       if (MODE == S_SYM) m = crecip(m);
-      v[e] = cmul(v[e], cscale(m, (Rr)sym.scale));
+      v[e] = cmul(v[e], m);
     }
     FftRun<C, N, E, +1, 1, typename PP::P>::run(v, tt, line, tws, BlockSync{});
   }

@@ -85,3 +85,41 @@ def test_batched_variants_and_graph_replays_identical():
             assert rel(to_np(a), to_np(r)) < 1e-9
     best = b.autotune(refine_every=20)
     assert 0 <= best <= 7
+
+
+def test_batched_1024_column_tiles_equal_single_solve():
+    """The grouped schedule keeps the complex64 spectrum of 1024^2 problems in
+    column tiles (a layout of its own); the solution must match the
+    single-problem refined solve (row-major spectrum), with every fused-pass
+    plan, and graph replays must reproduce the eager launch bit for bit."""
+    _need_gpu()
+    from paper_2207_14222_amd import solver
+    sizes = [1024, 64, 512]
+    print(f"[gpu-case] batch column tiles {sizes}", flush=True)
+    probs, cans, ops = _problems(sizes, seed0=4200)
+    xs = [torch.zeros_like(c.y) for c in cans]
+    b = solver.Batch(ops, [c.y for c in cans], xs, alpha=0.9, tol=1e-10, maxit=8000)
+    out = b.solve(refine_every=60, use_graph=False, variant=0)
+    assert out.worst == 0, out.status
+    xref = [x.clone() for x in xs]
+    for i, (can, op) in enumerate(zip(cans, ops)):
+        single = op.solve(can.y, alpha=0.9, tol=1e-10, maxit=8000, check_every=60)
+        assert single.converged
+        assert abs(out.iterations[i] - single.iterations) <= 60
+        assert rel(to_np(xs[i]), to_np(single.x)) < 1e-8, i
+        assert out.rho[i] < 1e-10
+    for v in (1, 2, 3):
+        runs = []
+        for graph in (False, True, True):
+            for x in xs:
+                x.fill_(3.0)
+            torch.cuda.synchronize()
+            o = b.solve(refine_every=60, use_graph=graph, variant=v)
+            assert o.worst == 0, o.status
+            runs.append((o.iterations, [x.clone() for x in xs]))
+        for it, xv in runs[1:]:
+            assert it == runs[0][0]
+            for a, r in zip(xv, runs[0][1]):
+                assert torch.equal(a, r)
+        for a, r in zip(runs[0][1], xref):
+            assert rel(to_np(a), to_np(r)) < 1e-9
