@@ -231,8 +231,10 @@ int usp_batch_workspace_bytes(const usp_batch_item* items, int nprob, size_t* by
 
 /* Solve every item with the refined method (complex64 iterations of
  * Algorithm 1, FP64 residual recomputed and accumulated every refine_every
- * iterations, stop at ||y - A x||/||y|| < tol; maxit is rounded up to a
- * multiple of refine_every).  variant: bits 0-1 select the fused-pass access
+ * iterations, stop at ||y - A x||/||y|| < tol).  A problem's cycle is cut to
+ * what remains of its maxit, and to the number of iterations that the rate
+ * of its FP64 residual over the previous cycle predicts for reaching tol when
+ * that is under half of refine_every.  variant: bits 0-1 select the fused-pass access
  * plan (bit 0 prefetch, bit 1 streaming); bit 2 selects the schedule:
  *   0 grouped: every launch covers the tiles of all active problems (the whole
  *     chip works on the batch); per-problem convergence, status and
