@@ -243,8 +243,10 @@ int usp_nn_features(const void* nidx, void* out, int D, int H, int W, double n_b
   if (!nidx || !out || D < 1 || H < 1 || W < 1 || plane < 0 || plane >= D || !(n_span > 0.0) || !(kappa_max > 0.0) ||
       !(w0 > 0.0))
     return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_features, dim3(grid_for((long)H * W, 64)), dim3(64), 0, (hipStream_t)stream, (const float2*)nidx,
-                     (uint16_t*)out, D, H, W, n_bg, n_span, kappa_max, plane, k0h, w0);
+  const long cols = (long)H * W;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((cols + kFeatCols - 1) / kFeatCols)), dim3(kFeatCols * kFeatSeg), 0,
+                     (hipStream_t)stream, (const float2*)nidx, (uint16_t*)out, D, H, W, n_bg, n_span, kappa_max, plane,
+                     k0h, w0);
   LAUNCHCHK("k_features");
   return 0;
 }

@@ -626,37 +626,78 @@ __device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane
   w[0] = pack8(f);
   w[1] = uint4{0u, 0u, 0u, 0u};
 }
-__global__ void k_features(const float2* __restrict__ nidx, uint16_t* __restrict__ out, int D, int H, int W,
-                           double n_bg, double n_span, double kappa_max, int plane, double k0h, double w0) {
-  constexpr int ZB = 16;  // planes whose loads are issued together
+// One block: kFeatCols (x, y) columns x kFeatSeg segments of z.  The path sums
+// are P(z) - P(plane) with P(z) the running trapezoid sum from z = 0: each
+// thread sums its segment, the segment sums are scanned through LDS (and P at
+// the source plane taken from its segment), then each thread walks its
+// segment again writing the features.
+constexpr int kFeatCols = 32, kFeatSeg = 8;
+__global__ void __launch_bounds__(kFeatCols * kFeatSeg)
+k_features(const float2* __restrict__ nidx, uint16_t* __restrict__ out, int D, int H, int W, double n_bg,
+           double n_span, double kappa_max, int plane, double k0h, double w0) {
+  __shared__ double segsum[kFeatSeg][kFeatCols][2];
+  __shared__ double pplane[kFeatCols][2];
   const long cols = (long)H * W;
-  for (long col = blockIdx.x * (long)blockDim.x + threadIdx.x; col < cols; col += (long)gridDim.x * blockDim.x) {
-    const double dx = (double)(col % W) - 0.5 * W, dy = (double)(col / W) - 0.5 * H;
-    const float amp = (float)exp(-(dx * dx + dy * dy) / (w0 * w0));
-    const float2 q0 = nidx[(long)plane * cols + col];
-    feature_row(out + ((long)plane * cols + col) * 16, q0, true, amp, 0.0, 0.0, k0h, n_bg, n_span, kappa_max);
-    // towards z = D - 1, then towards z = 0, ZB planes per batch of loads
-    for (int dir = 1; dir >= -1; dir -= 2) {
-      double pr = 0.0, pi = 0.0;
-      float2 prev = q0;
-      for (int zb = plane + dir; dir > 0 ? zb < D : zb >= 0; zb += dir * ZB) {
-        float2 q[ZB];
-#pragma unroll
-        for (int e = 0; e < ZB; ++e) {
-          const int z = zb + dir * e;
-          q[e] = (z >= 0 && z < D) ? nidx[(long)z * cols + col] : float2{0.f, 0.f};
-        }
-#pragma unroll
-        for (int e = 0; e < ZB; ++e) {
-          const int z = zb + dir * e;
-          if (z < 0 || z >= D) break;
-          pr += 0.5 * ((double)prev.x + q[e].x);
-          pi += 0.5 * ((double)prev.y + q[e].y);
-          prev = q[e];
-          feature_row(out + ((long)z * cols + col) * 16, q[e], false, amp, pr, pi, k0h, n_bg, n_span, kappa_max);
-        }
+  const int c = threadIdx.x % kFeatCols, sg = threadIdx.x / kFeatCols;
+  const long col = (long)blockIdx.x * kFeatCols + c;
+  const bool act = col < cols;
+  const int L = (D + kFeatSeg - 1) / kFeatSeg;
+  const int z0 = sg * L, z1 = min(D, z0 + L);
+  // trapezoid term of plane w >= 1: (n[w - 1] + n[w]) / 2
+  auto term = [&](int w, double& tr, double& ti) {
+    const float2 a = nidx[(long)(w - 1) * cols + col], b = nidx[(long)w * cols + col];
+    tr = 0.5 * ((double)a.x + b.x);
+    ti = 0.5 * ((double)a.y + b.y);
+  };
+  double sr = 0.0, si = 0.0;
+  if (act) {
+    for (int w = max(z0, 1); w < z1; ++w) {
+      double tr, ti;
+      term(w, tr, ti);
+      sr += tr;
+      si += ti;
+      if (w == plane) {   // P(plane) - P(z0 - 1 .. ) of this segment
+        pplane[c][0] = sr;
+        pplane[c][1] = si;
       }
     }
+  }
+  if (plane == 0 && sg == 0) {
+    pplane[c][0] = 0.0;
+    pplane[c][1] = 0.0;
+  }
+  segsum[sg][c][0] = sr;
+  segsum[sg][c][1] = si;
+  __syncthreads();
+  double p0r = 0.0, p0i = 0.0;   // P before this segment
+  for (int k = 0; k < sg; ++k) {
+    p0r += segsum[k][c][0];
+    p0i += segsum[k][c][1];
+  }
+  const int spl = plane / L;     // segment holding the source plane
+  double ppr = 0.0, ppi = 0.0;
+  for (int k = 0; k < spl; ++k) {
+    ppr += segsum[k][c][0];
+    ppi += segsum[k][c][1];
+  }
+  if (plane > 0 && max(spl * L, 1) <= plane) {
+    ppr += pplane[c][0];
+    ppi += pplane[c][1];
+  }
+  if (!act) return;
+  const double dx = (double)(col % W) - 0.5 * W, dy = (double)(col / W) - 0.5 * H;
+  const float amp = (float)exp(-(dx * dx + dy * dy) / (w0 * w0));
+  double Pr = p0r, Pi = p0i;
+  for (int z = z0; z < z1; ++z) {
+    if (z >= 1) {
+      double tr, ti;
+      term(z, tr, ti);
+      Pr += tr;
+      Pi += ti;
+    }
+    const double sgn = z >= plane ? 1.0 : -1.0;
+    feature_row(out + ((long)z * cols + col) * 16, nidx[(long)z * cols + col], z == plane, amp, sgn * (Pr - ppr),
+                sgn * (Pi - ppi), k0h, n_bg, n_span, kappa_max);
   }
 }
 

@@ -241,6 +241,28 @@ def test_features_against_oracle():
     assert float(got[5:].abs().max()) == 0.0
 
 
+@pytest.mark.parametrize("D,plane", [(13, 0), (13, 5), (13, 12), (4, 3), (17, 8)])
+def test_features_scan_depths_and_source_planes(D, plane):
+    """The z scan of the beam channels (segments of z summed, scanned, walked
+    again) for depths that do not split evenly into segments and source planes
+    at either end, through the C ABI, vs the float64 oracle to bf16 rounding."""
+    _need_gpu()
+    L = _lib()
+    print(f"[gpu-case] features D={D} plane={plane}", flush=True)
+    H, W = 6, 40
+    rng = np.random.default_rng(D * 31 + plane)
+    nidx = (1.33 + 0.17 * rng.random((D, H, W)) + 1j * 0.2 * rng.random((D, H, W))).astype(np.complex64)
+    out = torch.zeros(D * H * W * 16, dtype=torch.bfloat16, device="cuda")
+    nd = torch.from_numpy(nidx).cuda()
+    k0h, w0 = 0.5 * math.pi, 7.0
+    L.check(L.lib().usp_nn_features(_p(nd), _p(out), D, H, W, 1.33, 0.17, 0.2, plane, k0h, w0, _st()))
+    torch.cuda.synchronize()
+    got = to_cf(out, (D, H, W))
+    ref = S.features(nidx.astype(np.complex128), plane, w0, k0h)
+    assert float((got[:5] - torch.from_numpy(ref)).abs().max()) < 1e-2
+    assert float(got[5:].abs().max()) == 0.0
+
+
 def _oracle_params(net):
     P = {}
     for name, ly in net.layers.items():
