@@ -611,8 +611,8 @@ __global__ void k_add_bf(uint16_t* __restrict__ dst, const uint16_t* __restrict_
 // exp(-((x - W/2)^2 + (y - H/2)^2)/w0^2) carried along z with the phase and
 // attenuation of the medium, exp(i k0h sum (n + i kappa)) (trapezoid between
 // neighbouring planes, from the source plane up and down), channels 5..15
-// zero.  One thread per (x, y) column walks z; the path sums are in double,
-// the phase is reduced to [-pi, pi] in double before the float sine/cosine.
+// zero.  The path sums are in double, the phase is reduced to [-pi, pi] in
+// double before the float sine/cosine.
 __device__ __forceinline__ void feature_row(uint16_t* o, float2 q, bool on_plane, float amp, double pr, double pi,
                                             double k0h, double n_bg, double n_span, double kappa_max) {
   const float a = amp * expf((float)(-k0h * pi));
