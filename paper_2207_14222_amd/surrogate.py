@@ -128,25 +128,32 @@ class UNet3D:
         self.V = V
         a = Acts()
         a.x0 = torch.empty(V[0], 16, **bf)
-        a.e1a, a.e1 = torch.empty(V[0], 16, **bf), torch.empty(V[0], 16, **bf)
-        a.p1 = torch.empty(V[1], 16, **bf)
-        a.e2a, a.e2 = torch.empty(V[1], 32, **bf), torch.empty(V[1], 32, **bf)
-        a.p2 = torch.empty(V[2], 32, **bf)
-        a.e3a, a.e3 = torch.empty(V[2], 64, **bf), torch.empty(V[2], 64, **bf)
-        a.p3 = torch.empty(V[3], 64, **bf)
-        a.b = torch.empty(V[3], 128, **bf)
         a.c3, a.d3 = torch.empty(V[2], 192, **bf), torch.empty(V[2], 64, **bf)
         a.c2, a.d2 = torch.empty(V[1], 96, **bf), torch.empty(V[1], 32, **bf)
         a.c1, a.d1 = torch.empty(V[0], 48, **bf), torch.empty(V[0], 16, **bf)
+        # the skip activations are the leading 16-channel planes of the concat
+        # buffers (planes [C/16][V][16]), so the concatenation needs no copy
+        lead = lambda buf, v, c: buf.view(-1)[:v * c].view(v, c)
+        a.e1a, a.e1 = torch.empty(V[0], 16, **bf), lead(a.c1, V[0], 16)
+        a.p1 = torch.empty(V[1], 16, **bf)
+        a.e2a, a.e2 = torch.empty(V[1], 32, **bf), lead(a.c2, V[1], 32)
+        a.p2 = torch.empty(V[2], 32, **bf)
+        a.e3a, a.e3 = torch.empty(V[2], 64, **bf), lead(a.c3, V[2], 64)
+        a.p3 = torch.empty(V[3], 64, **bf)
+        a.b = torch.empty(V[3], 128, **bf)
         a.pred = torch.empty(V[0], 2, dtype=torch.float32, device=self.dev)
         self.a = a
         # gradient buffers
         def g(v, c):
             return torch.empty(V[v], c, **bf)
-        self.gb = {"c1": g(0, 48), "d1": g(0, 16), "e1": g(0, 16), "t1": g(0, 16),
-                   "c2": g(1, 96), "d2": g(1, 32), "e2": g(1, 32), "t2": g(1, 32), "p1": g(1, 16),
-                   "c3": g(2, 192), "d3": g(2, 64), "e3": g(2, 64), "t3": g(2, 64), "p2": g(2, 32),
+        self.gb = {"c1": g(0, 48), "d1": g(0, 16), "t1": g(0, 16),
+                   "c2": g(1, 96), "d2": g(1, 32), "t2": g(1, 32), "p1": g(1, 16),
+                   "c3": g(2, 192), "d3": g(2, 64), "t3": g(2, 64), "p2": g(2, 32),
                    "b": g(3, 128), "p3": g(3, 64)}
+        # likewise the skip part of each concat gradient is the skip gradient
+        self.gb["e1"] = lead(self.gb["c1"], V[0], 16)
+        self.gb["e2"] = lead(self.gb["c2"], V[1], 32)
+        self.gb["e3"] = lead(self.gb["c3"], V[2], 64)
         self.gout = g(0, 16)
         wsz = 0
         for n, ci, co, tp in LAYERS:
@@ -221,13 +228,10 @@ class UNet3D:
         self._conv("e3b", a.e3a, a.e3)
         self._pool(2, a.e3, a.p3)
         self._conv("b", a.p3, a.b)
-        self._copy(a.e3, 0, a.c3, 0, 64)
         self._up(2, a.b, a.c3, 128, 192, 64)
         self._conv("d3", a.c3, a.d3)
-        self._copy(a.e2, 0, a.c2, 0, 32)
         self._up(1, a.d3, a.c2, 64, 96, 32)
         self._conv("d2", a.c2, a.d2)
-        self._copy(a.e1, 0, a.c1, 0, 16)
         self._up(0, a.d2, a.c1, 32, 48, 16)
         self._conv("d1", a.c1, a.d1)
         self._conv("head", a.d1, a.pred, relu=False, out_f32=True, cstore=2)
@@ -253,19 +257,16 @@ class UNet3D:
         self._relu_back(a.d1, g["d1"], g["d1"])
         self._wgrad("d1", a.c1, g["d1"])
         self._conv_back("d1", g["d1"], g["c1"])              # gradient of concat(e1, up(d2))
-        self._copy(g["c1"], 0, g["e1"], 0, 16)
         self._up(0, g["c1"], g["d2"], 32, 48, 16, backward=True)
         # decoder level 2
         self._relu_back(a.d2, g["d2"], g["d2"])
         self._wgrad("d2", a.c2, g["d2"])
         self._conv_back("d2", g["d2"], g["c2"])
-        self._copy(g["c2"], 0, g["e2"], 0, 32)
         self._up(1, g["c2"], g["d3"], 64, 96, 32, backward=True)
         # decoder level 3
         self._relu_back(a.d3, g["d3"], g["d3"])
         self._wgrad("d3", a.c3, g["d3"])
         self._conv_back("d3", g["d3"], g["c3"])
-        self._copy(g["c3"], 0, g["e3"], 0, 64)
         self._up(2, g["c3"], g["b"], 128, 192, 64, backward=True)
         # bottleneck
         self._relu_back(a.b, g["b"], g["b"])
