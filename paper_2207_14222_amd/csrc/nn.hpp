@@ -300,14 +300,29 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
   for (int kc = 0; kc < KC; ++kc) {
     __syncthreads();  // the previous plane's reads are done
-    for (int u = tid; u < TL::PLANE_U4; u += 256) {
-      const int half = u & 1, vox = u >> 1;
-      const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
-      const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
-      uint4 q = uint4{0u, 0u, 0u, 0u};
-      if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-        q = in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
-      stg[u] = q;
+    // staged in batches of SB loads issued together, then stored: a load
+    // followed at once by its LDS store would wait out each load's latency
+    constexpr int NU = (TL::PLANE_U4 + 255) / 256, SB = 5;
+#pragma unroll
+    for (int k0 = 0; k0 < NU; k0 += SB) {
+      uint4 q[SB];
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int u = tid + 256 * (k0 + k);
+        q[k] = uint4{0u, 0u, 0u, 0u};
+        if (k0 + k < NU && u < TL::PLANE_U4) {
+          const int half = u & 1, vox = u >> 1;
+          const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
+          const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
+          if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+            q[k] = in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int u = tid + 256 * (k0 + k);
+        if (k0 + k < NU && u < TL::PLANE_U4) stg[u] = q[k];
+      }
     }
     __syncthreads();
     for (int tp = 0; tp < 14; ++tp) {
