@@ -300,9 +300,10 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
   for (int kc = 0; kc < KC; ++kc) {
     __syncthreads();  // the previous plane's reads are done
-    // staged in batches of SB loads issued together, then stored: a load
-    // followed at once by its LDS store would wait out each load's latency
-    constexpr int NU = (TL::PLANE_U4 + 255) / 256, SB = 5;
+    // every load of the plane is issued before the LDS stores (SB = NU: one
+    // batch; batches of 5 measured 2% slower): a load followed at once by its
+    // LDS store would wait out each load's latency
+    constexpr int NU = (TL::PLANE_U4 + 255) / 256, SB = NU;
 #pragma unroll
     for (int k0 = 0; k0 < NU; k0 += SB) {
       uint4 q[SB];
