@@ -300,30 +300,33 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
   const uint4* in4 = reinterpret_cast<const uint4*>(in);
   for (int kc = 0; kc < KC; ++kc) {
     __syncthreads();  // the previous plane's reads are done
-    // every load of the plane is issued before the LDS stores (SB = NU: one
-    // batch; batches of 5 measured 2% slower): a load followed at once by its
-    // LDS store would wait out each load's latency
-    constexpr int NU = (TL::PLANE_U4 + 255) / 256, SB = NU;
+    auto stage = [&](int u) -> uint4 {
+      const int half = u & 1, vox = u >> 1;
+      const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
+      const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
+      if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
+        return in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
+      return uint4{0u, 0u, 0u, 0u};
+    };
+    if constexpr (KC <= 3) {
+      // every load of the plane is issued before the LDS stores: a load
+      // followed at once by its store would wait out each load's latency
+      // (batches of 5 measured 2% slower; with more input planes the held
+      // loads cost occupancy and the plain loop below was faster)
+      constexpr int NU = (TL::PLANE_U4 + 255) / 256;
+      uint4 q[NU];
 #pragma unroll
-    for (int k0 = 0; k0 < NU; k0 += SB) {
-      uint4 q[SB];
-#pragma unroll
-      for (int k = 0; k < SB; ++k) {
-        const int u = tid + 256 * (k0 + k);
-        q[k] = uint4{0u, 0u, 0u, 0u};
-        if (k0 + k < NU && u < TL::PLANE_U4) {
-          const int half = u & 1, vox = u >> 1;
-          const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
-          const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
-          if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
-            q[k] = in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
-        }
+      for (int k = 0; k < NU; ++k) {
+        const int u = tid + 256 * k;
+        q[k] = u < TL::PLANE_U4 ? stage(u) : uint4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
-      for (int k = 0; k < SB; ++k) {
-        const int u = tid + 256 * (k0 + k);
-        if (k0 + k < NU && u < TL::PLANE_U4) stg[u] = q[k];
+      for (int k = 0; k < NU; ++k) {
+        const int u = tid + 256 * k;
+        if (u < TL::PLANE_U4) stg[u] = q[k];
       }
+    } else {
+      for (int u = tid; u < TL::PLANE_U4; u += 256) stg[u] = stage(u);
     }
     __syncthreads();
     for (int tp = 0; tp < 14; ++tp) {
