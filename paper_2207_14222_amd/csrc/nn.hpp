@@ -198,11 +198,15 @@ __device__ __forceinline__ void conv_store(const v4f& acc, int t, long v0, int l
 // (27-tap packing), operands loaded from global memory.  One wave computes MV
 // tiles of 16 consecutive voxels x all COUT channels.  For grids too small or
 // too irregular for the LDS-staged kernel.
-template <int CIN, int COUT, int SIGN, bool RELU, int MV>
+// TS > 1 (small grids): the output tiles are split over TS blocks
+// (blockIdx.y takes tiles [y NT/TS, (y + 1) NT/TS)), for TS times the waves.
+template <int CIN, int COUT, int SIGN, bool RELU, int MV, int TS = 1>
 __global__ void __launch_bounds__(256)
 k_conv27(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const float* __restrict__ bias,
          uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore, int D, int H, int W) {
-  constexpr int NT = COUT / 16, KC = CIN / 16;
+  constexpr int NTA = COUT / 16, NT = NTA / TS, KC = CIN / 16;
+  static_assert(NTA % TS == 0, "tile split");
+  const int t0 = blockIdx.y * NT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int V = D * H * W;
   const int vw = (blockIdx.x * 4 + wave) * (16 * MV);
@@ -240,7 +244,7 @@ k_conv27(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const f
     for (int kc = 0; kc < KC; ++kc) {
       v8bf b[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) b[t] = as_v8bf(wpk[((tp * KC + kc) * NT + t) * 64 + lane]);
+      for (int t = 0; t < NT; ++t) b[t] = as_v8bf(wpk[((tp * KC + kc) * NTA + t0 + t) * 64 + lane]);
 #pragma unroll
       for (int m = 0; m < MV; ++m) {
         const uint4 q = ok[m] ? *reinterpret_cast<const uint4*>(in + ((long)kc * V + nb[m]) * 16 + 8 * (g & 1))
@@ -253,10 +257,10 @@ k_conv27(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const f
   }
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
-    const float bb = bias ? bias[t * 16 + (lane & 15)] : 0.f;
+    const float bb = bias ? bias[(t0 + t) * 16 + (lane & 15)] : 0.f;
 #pragma unroll
     for (int m = 0; m < MV; ++m)
-      if (live[m]) conv_store<RELU>(acc[m][t], t, vw + 16 * m, lane, bb, V, out_bf, out_f32, cstore);
+      if (live[m]) conv_store<RELU>(acc[m][t], t0 + t, vw + 16 * m, lane, bb, V, out_bf, out_f32, cstore);
   }
 }
 
