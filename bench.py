@@ -485,8 +485,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU decomposition is "
-              "design-only, see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); no multi-GPU path is built "
+              "(independent problems and slabs of one grid would shard across GPUs, but that is not implemented)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
