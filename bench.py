@@ -130,10 +130,11 @@ def bench_diffusion(args, log):
 
 def bench_batch(args, log):
     """96 independent 2-D Helmholtz problems (sides drawn from {128, 256, 512, 1024},
-    random disks, beam on row 20; seeds 4 / 4000+i) solved in one persistent launch
-    (complex64 + FP64 refinement every 60, tol 1e-6, alpha 0.9: measured 1.34 s with
-    every 20 and alpha 0.8), against solving the same problems one at a time (plain
-    complex128 checked every 20, and refined complex64 every 60)."""
+    random disks, beam on row 20; seeds 4 / 4000+i) solved together by the autotuned
+    batched schedule (grouped graph-captured launches in practice; complex64 + FP64
+    refinement every --batch-refine-every iterations with each problem's final cycle
+    predicted, tol 1e-6, alpha 0.9), against solving the same problems one at a time
+    (plain complex128 checked every 20, and refined complex64)."""
     import torch
     from paper_2207_14222_amd import media, solver
     sizes = media.batch_sizes(args.batch_n, seed=4)

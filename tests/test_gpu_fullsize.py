@@ -1,7 +1,9 @@
 """Parity at the benchmark sizes, in the launch configuration bench.py times
 (autotuned plans, refined complex64): K full iterations compared element by
 element with the FP64 oracle's iterates, plus the solution against the
-oracle's residual (a property that holds at any size)."""
+oracle's residual (a property that holds at any size); the batched workload
+as bench.py runs it, with a sample of its solutions checked by the oracle's
+residual."""
 import numpy as np
 import pytest
 
@@ -74,3 +76,34 @@ def test_batch_largest_size_iterates():
     op = solver.Operator(can.symbol, can.B)
     x, _ = op.iterate(can.y, alpha=0.8, K=5)
     assert rel(to_np(x), xo) < 3e-5
+
+
+def test_batched_workload_solutions_by_oracle_residual():
+    """The batched workload as bench.py runs it (96 problems, sides from
+    {128, 256, 512, 1024} drawn with seed 4, disks with seeds 4000 + i; grouped
+    schedule with the streamed fused-pass plan, refinement interval 150 with
+    the final cycle predicted per problem, alpha 0.9, tol 1e-6): every problem
+    converges, and for three problems of each size the solution's residual
+    recomputed by the oracle is below 1e-6."""
+    _need_gpu()
+    from paper_2207_14222_amd import solver
+    print("[gpu-case] batched workload 96 problems", flush=True)
+    sizes = media.batch_sizes(96, seed=4)
+    probs, cans, ops = [], [], []
+    for i, n in enumerate(sizes):
+        p = media.helmholtz_disks(n=n, seed=4000 + i)
+        probs.append(p)
+        cans.append(solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex128))
+        ops.append(solver.Operator(cans[-1].symbol, cans[-1].B, refine=True))
+    xs = [torch.zeros_like(c.y) for c in cans]
+    b = solver.Batch(ops, [c.y for c in cans], xs, alpha=0.9, tol=1e-6, maxit=20000)
+    out = b.solve(refine_every=150, use_graph=True, variant=2)
+    assert out.worst == 0, out.status
+    assert max(out.rho) < 1e-6
+    for n in (128, 256, 512, 1024):
+        for i in [j for j, m in enumerate(sizes) if m == n][:3]:
+            p = probs[i]
+            cp = canon.canonical_helmholtz(p.k2, p.source, p.spacing)
+            rho = R.relative_residual(operators.Operator(cp), to_np(xs[i]), cp.y)
+            assert rho < 1e-6, (i, n, rho)
+            assert abs(rho - out.rho[i]) < 1e-9, (i, n, rho, out.rho[i])
