@@ -1,5 +1,9 @@
-"""Batched persistent solve (one launch, many uneven-size 2-D problems) against the
-single-problem refined solve and the FP64 oracle."""
+"""Batched solve of many uneven-size 2-D problems (grouped graph-captured
+launches and the one-launch persistent schedule) against the single-problem
+refined solve and the FP64 oracle: both schedules give the same iteration
+counts and solutions, every fused-pass plan and graph replay reproduces the
+eager launch bit for bit, and 1024^2 problems (column-tiled spectrum) match
+the single-problem solve."""
 import numpy as np
 import pytest
 
