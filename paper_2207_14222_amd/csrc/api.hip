@@ -694,9 +694,13 @@ int solve_bicgstab(usp_op op, const C* y, C* x, int x_is_guess, double tol, int 
 // rows it needs in the same fixed order, so no scalar kernel or host round
 // trip sits between them; |r|^2 alternates between two rows (2 and 3).  The
 // host synchronises at true-residual checks only.
+// first_check > 0: the first check at that iteration, then every check_every
+// (a caller that knows roughly how many iterations a solve takes checks
+// around the end only); 0: every check_every from the start.
 template <class C>
 int solve_cg(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit, int check_every, const KWork& kw,
-             int* iters_out, Monitor& mon) {
+             int* iters_out, Monitor& mon, int first_check = 0) {
+  if (first_check <= 0) first_check = check_every;
   const long n = op->d.N;
   const Dims& D = op->d;
   const int nlines = D.n0 * D.n1;
@@ -742,7 +746,7 @@ int solve_cg(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit,
                        rrow[cur ^ 1], ks);
     LAUNCHCHK("cg iteration");
     ++it;
-    if (it % check_every == 0 || it == maxit) {
+    if ((it >= first_check && (it - first_check) % check_every == 0) || it == maxit) {
       double rho, hk[2];
       if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
       if ((rc = ksum(op, kw, 2 + (it & 1), 1, vb, ks + KS_CRR))) return rc;   // |r_it|^2
@@ -969,14 +973,21 @@ int eigs_run(usp_op op, int nev, int ncv, const C* v0, double tol, int max_resta
     HIPCHK(hipStreamSynchronize(op->st));   // cbuf is reused by the next call
     return 0;
   };
+  // the inner solves share the operator and the tolerance, so they take
+  // similar iteration counts: the true residual is checked every 5
+  // iterations from 4 before the previous solve's count (every 10 for the first)
+  int prev_its = 0;
   for (cycle = 0; cycle <= max_restarts && !done; ++cycle) {
     m = ncv;
     for (int j = k; j < ncv; ++j) {
       // w = A^-1 v_j (CG on P w = B (L + I)^-1 v_j from w = 0)
       Monitor imon{nullptr, 0, nullptr, 0};
       int its = 0;
-      rc = solve_cg<C>(op, basis(j), w, 0, inner_tol, inner_maxit, 10, kw, &its, imon);
+      rc = prev_its > 0 ? solve_cg<C>(op, basis(j), w, 0, inner_tol, inner_maxit, 5, kw, &its, imon,
+                                      std::max(5, prev_its - 4))
+                        : solve_cg<C>(op, basis(j), w, 0, inner_tol, inner_maxit, 10, kw, &its, imon);
       total_inner += its;
+      if (rc == USP_OK) prev_its = its;
       if (rc < 0) return rc;
       // classical Gram-Schmidt against v_0 .. v_j, twice
       for (int pass = 0; pass < 2; ++pass) {
