@@ -9,12 +9,41 @@ l(p) = s (a0 + a2 |p|^2 + a1 i p); for the first-derivative (1-D) symbol the
 Nyquist mode of i p is set to zero so that d/dt stays skew-Hermitian.
 (L + I)^-1 = F^-1 diag(1/(l(p) + 1)) F, which for Helmholtz is exactly
 F^-1 c/(-|p|^2 + kbar^2 + c) F.
+
+The multi-dimensional transforms F and F^-1 are a library routine: pocketfft
+through ``scipy.fft`` with FFT_WORKERS threads (numpy.fft, the same algorithm
+single-threaded, when SciPy is absent).  Both are pinned against a naive DFT
+over every axis in the tests.
 """
 from __future__ import annotations
+
+import os
 
 import numpy as np
 
 from .canon import Canonical
+
+try:
+    import scipy.fft as _sfft
+except ImportError:  # pragma: no cover
+    _sfft = None
+
+# threads of the library FFT (the host's cores, at most 16)
+FFT_WORKERS = max(1, min(16, os.cpu_count() or 1))
+
+
+def fftn(x):
+    """Unnormalised forward DFT over all axes."""
+    if _sfft is not None:
+        return _sfft.fftn(x, workers=FFT_WORKERS)
+    return np.fft.fftn(x)
+
+
+def ifftn(x):
+    """Inverse DFT over all axes, with the 1/N."""
+    if _sfft is not None:
+        return _sfft.ifftn(x, workers=FFT_WORKERS)
+    return np.fft.ifftn(x)
 
 
 def wavenumbers(n: int, h: float) -> np.ndarray:
@@ -72,11 +101,11 @@ class Operator:
 
     # L, (L + I)^-1, A ----------------------------------------------------
     def apply_L(self, x):
-        return np.fft.ifftn(self.l * np.fft.fftn(x))
+        return ifftn(self.l * fftn(x))
 
     def apply_LI_inv(self, t):
         """(L + I)^-1 t = F^-1 [ F t / (l + 1) ]   (Eq. laplacian_inverse)."""
-        return np.fft.ifftn(np.fft.fftn(t) / (self.l + 1.0))
+        return ifftn(fftn(t) / (self.l + 1.0))
 
     def apply_A(self, x):
         return self.apply_L(x) + self.apply_V(x)

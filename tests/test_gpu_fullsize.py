@@ -1,9 +1,8 @@
-"""Parity at the benchmark sizes, in the launch configuration bench.py times
-(autotuned plans, refined complex64): K full iterations compared element by
-element with the FP64 oracle's iterates, plus the solution against the
-oracle's residual (a property that holds at any size); the batched workload
-as bench.py runs it, with a sample of its solutions checked by the oracle's
-residual."""
+"""Parity at the sizes of the other benchmark workloads (the 256^3 Helmholtz
+workload is covered with the headline path's tests): complex64 iterates of the
+256 x 256 x 128 diffusion and the largest batched size element by element
+against the FP64 oracle, and the batched workload as bench.py runs it, with a
+sample of its solutions checked by the oracle's residual."""
 import numpy as np
 import pytest
 
@@ -21,33 +20,6 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_helmholtz_256cubed_iterates_and_solution():
-    """256^3 spheres (seed 2): 3 complex64 iterations vs the oracle; refined solve's
-    final x has oracle residual < 1e-6."""
-    _need_gpu()
-    from paper_2207_14222_amd import solver
-    print("[gpu-case] 256^3 helmholtz full size", flush=True)
-    p = media.helmholtz_spheres(shape=(256, 256, 256), seed=2)
-    cp = canon.canonical_helmholtz(p.k2, p.source, p.spacing)
-    op_o = operators.Operator(cp)
-    K = 3
-    xo, ho = R.iterate(op_o, cp.y, 0.8, K)
-    can64 = solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex64)
-    op64 = solver.Operator(can64.symbol, can64.B)
-    xt = torch.zeros_like(can64.y)
-    op64.autotune(can64.y, xt, alpha=0.8, reps=2)
-    x, h = op64.iterate(can64.y, alpha=0.8, K=K)
-    assert rel(to_np(x), xo) < 3e-5
-    np.testing.assert_allclose(np.sqrt(h), ho, rtol=1e-4)
-    del op64, can64, x
-    can = solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex128)
-    op = solver.Operator(can.symbol, can.B, refine=True)
-    res = op.solve(can.y, alpha=0.8, tol=1e-6, maxit=2000, check_every=20)
-    assert res.converged
-    xs = to_np(res.x)
-    assert R.relative_residual(op_o, xs, cp.y) < 1e-6
-
-
 def test_diffusion_full_size_iterates():
     """256 x 256 x 128 frequency-domain diffusion (seed 3): complex64 iterates vs the oracle."""
     _need_gpu()
@@ -56,10 +28,10 @@ def test_diffusion_full_size_iterates():
     d = media.diffusion_blobs(seed=3)
     cp = canon.canonical_diffusion(d.mu_a, d.D, d.omega_over_v, d.source, d.spacing)
     op_o = operators.Operator(cp)
-    xo, _ = R.iterate(op_o, cp.y, 1.0, 3)
+    xo, _ = R.iterate(op_o, cp.y, 1.0, 20)
     can = solver.canonical_diffusion(d.mu_a, d.D, d.omega_over_v, d.source, d.spacing, dtype=torch.complex64)
     op = solver.Operator(can.symbol, can.B)
-    x, _ = op.iterate(can.y, alpha=1.0, K=3)
+    x, _ = op.iterate(can.y, alpha=1.0, K=20)
     assert rel(to_np(x), xo) < 3e-5
 
 
@@ -71,10 +43,10 @@ def test_batch_largest_size_iterates():
     p = media.helmholtz_disks(n=1024, seed=4000)
     cp = canon.canonical_helmholtz(p.k2, p.source, p.spacing)
     op_o = operators.Operator(cp)
-    xo, _ = R.iterate(op_o, cp.y, 0.8, 5)
+    xo, _ = R.iterate(op_o, cp.y, 0.8, 20)
     can = solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex64)
     op = solver.Operator(can.symbol, can.B)
-    x, _ = op.iterate(can.y, alpha=0.8, K=5)
+    x, _ = op.iterate(can.y, alpha=0.8, K=20)
     assert rel(to_np(x), xo) < 3e-5
 
 

@@ -24,6 +24,23 @@ def test_fft_matches_naive_dft(n):
     assert np.allclose(np.fft.ifft(naive_dft(x)), x, atol=1e-13 * n)
 
 
+@pytest.mark.parametrize("shape", [(8,), (4, 8), (2, 4, 8), (8, 4, 2)])
+def test_oracle_fftn_matches_naive_dft(shape):
+    """The oracle's multi-dimensional transform (library FFT, threaded) against a
+    naive DFT matrix applied along every axis, forward and inverse."""
+    rng = np.random.default_rng(len(shape))
+    x = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    ref = x
+    for ax in range(len(shape)):
+        n = shape[ax]
+        j = np.arange(n)
+        W = np.exp(-2j * np.pi * np.outer(j, j) / n)
+        ref = np.moveaxis(np.tensordot(W, np.moveaxis(ref, ax, 0), axes=(1, 0)), 0, ax)
+    N = x.size
+    assert np.allclose(operators.fftn(x), ref, rtol=0, atol=1e-12 * N)
+    assert np.allclose(operators.ifftn(ref), x, rtol=0, atol=1e-13 * N)
+
+
 def test_wavenumbers():
     for n, h in ((8, 0.25), (7, 0.5), (16, 1.0)):
         p = operators.wavenumbers(n, h)
