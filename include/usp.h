@@ -69,7 +69,8 @@ extern "C" {
  *     l(p) = s * (a0 + a2 |p|^2 + a1 * i * p_0)        (a1 term: ndim == 1 only)
  * on the FFT grid p_k = 2 pi fftfreq(n_k, h_k).  When nyquist_zero is set, the
  * first-derivative term i p is zero at the Nyquist index (keeps d/dt
- * skew-Hermitian).  Complex coefficients are (re, im) pairs.
+ * skew-Hermitian).  Complex coefficients are (re, im) pairs.  A 2-D or 3-D
+ * symbol with a1 != 0 or nyquist_zero set is rejected (USP_ERR_INVALID).
  *   Helmholtz:  s = 1/c, a0 = kbar^2, a2 = -1            (c = i R / 0.95)
  *   diffusion:  s = 1/c, a0 = mubar - i omega/v, a2 = D  (c = R / 0.95)
  *   pantograph: s = 1/c, a0 = abar, a1 = 1               (c real)
@@ -105,12 +106,15 @@ typedef struct usp_op_s* usp_op;
  *               (streaming) accesses so the temporary spectrum stays cached
  *   w_mid       column-tile width (elements, 4/8/16/32; 0 = default) of the
  *               middle-axis passes (3-D)
- *   w_sym       column-tile width of the symbol pass (first axis) */
+ *   w_sym       column-tile width of the symbol pass (first axis)
+ *   r_load      FP64 residual's last pass: bit 0 loads x, B, y before its
+ *               inverse FFT, bit 1 reads them with non-temporal accesses */
 typedef struct {
   int x_prefetch;
   int w_mid;
   int w_sym;
   int x_stream;
+  int r_load;
 } usp_plan;
 
 /* Workspace size for an operator.  dtype: USP_C64 or USP_C128; flags: 0 or
@@ -200,9 +204,17 @@ int usp_set_plan(usp_op op, const usp_plan* plan);
 
 /* Autotuner: times `reps` iterations (best of two) for every candidate plan on
  * y_dev / x_dev (x_dev overwritten; in refined mode the workspace copies are
- * used) and keeps the fastest in the handle; best_out may be NULL.  Results of
- * all candidates are identical, so tuning never changes a solution. */
+ * used) and keeps the fastest in the handle, then times one FP64 residual of
+ * x_dev for each r_load and keeps the fastest; best_out may be NULL.  Results
+ * of all candidates are identical, so tuning never changes a solution. */
 int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int reps, usp_plan* best_out);
+
+/* Measurement hook (not part of the method): copy `bytes` bytes from src_dev
+ * to dst_dev on `stream` with non-temporal 16-byte loads and stores, the
+ * streaming ceiling that the pass kernels' HBM rates are compared with.  Both
+ * pointers 16-byte aligned, bytes a multiple of 16, buffers not overlapping
+ * (USP_ERR_INVALID otherwise).  Asynchronous. */
+int usp_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream);
 
 /* ---- batched persistent solve (many uneven-size 2-D problems) ----------- */
 
@@ -296,6 +308,17 @@ int usp_canonical_helmholtz(const double* k2_host, size_t n, int bias_kind, cons
 int usp_canonical_diffusion(const double* mu_host, size_t n, double D, double omega_over_v, double vnorm,
                             const usp_symbol* grid, usp_symbol* sym_out, double* c_out, double* bias_out);
 
+/* Shifted Schrodinger operator (Sec. 4, Eq. schrodinger; unit mass, natural
+ * units): H + shift = -1/2 laplacian + V + shift on the grid, canonicalised as
+ * the constant-D diffusion operator with D = 1/2, mu = V + shift, omega = 0.
+ * V_host: n real potential values.  c = (max V - min V)/(2 vnorm);
+ * sym_out: s = 1/c, a0 = midrange(V) + shift, a2 = 1/2; bias_out = the field
+ * bias midrange(V) for usp_canonical_fields(V, S, bias, c, +1, ...), which
+ * gives B = 1 - (V - midrange(V))/c.  Energies: E = c lam - shift.  A constant
+ * V (R = 0) or a non-finite value: USP_ERR_INVALID / USP_ERR_NAN.  Host only. */
+int usp_canonical_schrodinger(const double* V_host, size_t n, double shift, double vnorm, const usp_symbol* grid,
+                              usp_symbol* sym_out, double* c_out, double* bias_out);
+
 /* Pantograph canonical form (Sec. 3.3, Eq. pantograph-A) on t_j = t0 + j h:
  * A x = c^-1 [(d/dt + a) x + b x(lam t)], y = c^-1 [b x0(lam t) + x0(t0) delta(t - t0)],
  * the delta sampled as x0(t0)/h at j = 0.  Inputs (host, n complex = 2n doubles):
@@ -304,7 +327,11 @@ int usp_canonical_diffusion(const double* mu_host, size_t n, double D, double om
  * gather S; c = (sup|a - abar| + sup|b| ||S||_2)/vnorm (real), which bounds
  * ||V|| by vnorm.  Outputs (host): sym_out (s = 1/c, a0 = abar, a1 = 1,
  * nyquist_zero = 1), B_out = 1 - (a - abar)/c, gather idx_out / g0_out / g1_out
- * (usp_gather layout), y_out, c_out, bias_out (2 doubles each). */
+ * (usp_gather layout), y_out, c_out, bias_out (2 doubles each).  For the
+ * antisymmetrised form (USP_FLAG_ANTISYM) the caller clears
+ * sym_out->nyquist_zero: with a zero derivative at the Nyquist index the
+ * alternating grid vector is almost in the null space of A (the interpolation
+ * gather nearly annihilates it) and the iteration stalls. */
 int usp_canonical_pantograph(const double* a, const double* b, int n, double lam, double t0, double h,
                              const double* x0_lam_t, const double* x0_t0, double vnorm, usp_symbol* sym_out,
                              double* B_out, int32_t* idx_out, double* g0_out, double* g1_out, double* y_out,

@@ -244,7 +244,7 @@ def gather_matrix(n, idx, w0, w1):
     return S
 
 
-def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm=VNORM):
+def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm=VNORM, nyquist_zero=True):
     """Pantograph splitting (Sec. 3.3, Eq. pantograph-A).
 
     A x = c^-1 [(d/dt + a) x + b x(lam t)],  y = c^-1 [b x0(lam t) + x0(t0) delta(t - t0)].
@@ -253,7 +253,12 @@ def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm=VNORM):
     ||V|| only if the dilation gather has norm <= 1; for the discrete linear
     interpolation gather its spectral norm ||S|| exceeds 1 when lam < 1, so the
     scale used is c = (sup|a - abar| + sup|b| ||S||_2)/0.95, which restores ||V|| <= 0.95.
-    Symbol: s = 1/c, a0 = abar, a1 = 1 (l(p) = (i p + abar)/c, Nyquist mode of i p = 0).
+    Symbol: s = 1/c, a0 = abar, a1 = 1 (l(p) = (i p + abar)/c).  With nyquist_zero the
+    Nyquist mode of i p is 0 (the direct form; it keeps real signals real); without it
+    p = -pi/h there, which the antisymmetrised form needs: F^-1 diag(i p) F is
+    skew-Hermitian for any real p, while a zero derivative at the Nyquist index
+    leaves the alternating grid vector almost in the null space of A (the
+    interpolation gather nearly annihilates it), which stalls the iteration.
     """
     a = np.asarray(a, dtype=np.complex128)
     b = np.asarray(b, dtype=np.complex128)
@@ -271,4 +276,4 @@ def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm=VNORM):
     g1 = (b * w1) / c
     return Canonical(shape=(n,), spacing=(h,), s=1.0 / c, a0=abar, a1=1.0, a2=0.0, v=v, y=y, c=c,
                      bias=abar, gi=idx, g0=g0.astype(np.complex128), g1=g1.astype(np.complex128),
-                     nyquist_zero=True, extra={"gather_norm": snorm})
+                     nyquist_zero=bool(nyquist_zero), extra={"gather_norm": snorm})

@@ -34,7 +34,8 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_nn_pred_to_field", "usp_krylov_workspace_bytes", "usp_solve_krylov", "usp_apply_precond",
            "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual",
            "usp_flux_refined_workspace_bytes", "usp_flux_solve_refined",
-           "usp_eigs_workspace_bytes", "usp_eigs", "usp_hermitian_eig"]
+           "usp_eigs_workspace_bytes", "usp_eigs", "usp_hermitian_eig", "usp_stream_copy",
+           "usp_canonical_schrodinger"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -46,7 +47,8 @@ class usp_symbol(ct.Structure):
 
 
 class usp_plan(ct.Structure):
-    _fields_ = [("x_prefetch", ct.c_int), ("w_mid", ct.c_int), ("w_sym", ct.c_int), ("x_stream", ct.c_int)]
+    _fields_ = [("x_prefetch", ct.c_int), ("w_mid", ct.c_int), ("w_sym", ct.c_int), ("x_stream", ct.c_int),
+                ("r_load", ct.c_int)]
 
 
 class usp_batch_item(ct.Structure):
@@ -100,11 +102,13 @@ def lib():
     SP = ct.POINTER(usp_symbol)
     L.usp_canonical_helmholtz.argtypes = [DP, Z, I, DP, D, SP, SP, DP, DP]
     L.usp_canonical_diffusion.argtypes = [DP, Z, D, D, D, SP, SP, DP, DP]
+    L.usp_canonical_schrodinger.argtypes = [DP, Z, D, D, SP, SP, DP, DP]
     L.usp_profile.argtypes = [P, P, P, D, I, DP, DP]
     PP = ct.POINTER(usp_plan)
     L.usp_get_plan.argtypes = [P, PP]
     L.usp_set_plan.argtypes = [P, PP]
     L.usp_autotune.argtypes = [P, P, P, D, I, PP]
+    L.usp_stream_copy.argtypes = [P, P, Z, P]
     BI = ct.POINTER(usp_batch_item)
     L.usp_batch_workspace_bytes.argtypes = [BI, I, ct.POINTER(Z)]
     L.usp_solve_batched.argtypes = [BI, I, I, I, P, Z, P, I, ct.POINTER(usp_batch_result), DP]

@@ -62,13 +62,18 @@ template <class Cc> int x_blocks(usp_op op) {
   return nb;
 }
 
-// add up `nrows` partial rows starting at `row` (ncols partials each) into
-// out[(first + r) % nmod]
-int sum_rows(usp_op op, int row, int nrows, int ncols, double* out, int first, int nmod) {
+// add up `nrows` partial rows starting at `row` (ncols partials each, FP32 if
+// f32 else FP64) into out[(first + r) % nmod]
+int sum_rows(usp_op op, int row, int nrows, int ncols, double* out, int first, int nmod, bool f32 = false) {
   if (nrows <= 0) return 0;
   prof_mark(op);
-  hipLaunchKernelGGL(k_sum_rows, dim3(nrows), dim3(256), 0, op->st, op->partials + (long)row * op->pitch, op->pitch,
-                     ncols, out, first, nmod);
+  if (f32)
+    hipLaunchKernelGGL(k_sum_rows<float>, dim3(nrows), dim3(256), 0, op->st,
+                       reinterpret_cast<const float*>(op->partials + (long)row * op->pitch), 2 * op->pitch, ncols,
+                       out, first, nmod);
+  else
+    hipLaunchKernelGGL(k_sum_rows<double>, dim3(nrows), dim3(256), 0, op->st, op->partials + (long)row * op->pitch,
+                       op->pitch, ncols, out, first, nmod);
   prof_mark(op);
   LAUNCHCHK("k_sum_rows");
   return 0;
@@ -78,7 +83,7 @@ int sum_rows(usp_op op, int row, int nrows, int ncols, double* out, int first, i
 int finalize_hist(usp_op op) {
   const int kind = op->kind;
   op->kind = USP_PASS_REDUCE;
-  int rc = sum_rows(op, 0, op->pending, op->xblocks, op->hist, op->pending_first, kHist);
+  int rc = sum_rows(op, 0, op->pending, op->xblocks, op->hist, op->pending_first, kHist, op->pending_f32);
   op->kind = kind;
   op->pending_first += op->pending;
   op->pending = 0;
@@ -91,7 +96,8 @@ int launch_x(usp_op op, Cc* t, Cx* x, const Cx* y, const Cx* B, const float2* d,
              int has_x, RedArgs red) {
   const Dims& D = op->d;
   const int nlines = D.n0 * D.n1;
-  const int fl = (MODE == X_FUSED) ? ((op->plan.x_prefetch ? 1 : 0) | (op->plan.x_stream ? 2 : 0)) : 0;
+  const int fl = (MODE == X_FUSED) ? ((op->plan.x_prefetch ? 1 : 0) | (op->plan.x_stream ? 2 : 0))
+                 : (MODE == X_RINV) ? (op->plan.r_load & 3) : 0;
   bool ok = with_n(D.n2, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     constexpr int E = PassPlan<N>::E, T = N / E;
@@ -208,6 +214,8 @@ int iteration(usp_op op, C* x, const C* y, const C* B, double alpha) {
   if (op->d.ndim == 3 && (rc = launch_s<C, S_INV>(op, t, 1, sa, wm))) return rc;
   op->kind = 0;
   if ((rc = launch_x<C, C, X_FUSED>(op, t, x, y, B, nullptr, nullptr, alpha, 1, red_row(op, op->pending)))) return rc;
+  // a solve finalises the pending rows before it switches precision
+  op->pending_f32 = sizeof(C) == 8;
   if (++op->pending == kRows) return finalize_hist(op);
   return 0;
 }
@@ -558,8 +566,8 @@ int vec_blocks(long n) { return (int)std::min<long>((n + 255) / 256, kVecBlocks)
 
 // add rows [row0, row0 + nrows) of `ncols` partials each into out[0 .. nrows)
 int ksum(usp_op op, const KWork& kw, int row0, int nrows, int ncols, double* out) {
-  hipLaunchKernelGGL(k_sum_rows, dim3(nrows), dim3(256), 0, op->st, kw.rows + (long)row0 * kw.pitch, kw.pitch, ncols,
-                     out, 0, 1 << 30);
+  hipLaunchKernelGGL(k_sum_rows<double>, dim3(nrows), dim3(256), 0, op->st, kw.rows + (long)row0 * kw.pitch, kw.pitch,
+                     ncols, out, 0, 1 << 30);
   LAUNCHCHK("k_sum_rows");
   return 0;
 }
@@ -1546,6 +1554,7 @@ int usp_set_plan(usp_op op, const usp_plan* plan) {
   if (!op || !plan) return fail(USP_ERR_INVALID, "NULL argument");
   for (int w : {plan->w_mid, plan->w_sym})
     if (!(w == 0 || w == 4 || w == 8 || w == 16 || w == 32)) return fail(USP_ERR_INVALID, "tile width must be 0, 4, 8, 16 or 32");
+  if (plan->r_load < 0 || plan->r_load > 3) return fail(USP_ERR_INVALID, "r_load must be 0 to 3");
   op->plan = *plan;
   return 0;
 }
@@ -1563,7 +1572,7 @@ int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int re
   for (int fl = 0; fl < 4; ++fl)
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
-        usp_plan p{};
+        usp_plan p = op->plan;
         p.x_prefetch = fl & 1;
         p.x_stream = (fl >> 1) & 1;
         p.w_mid = op->d.ndim == 3 ? ws[a] : 0;
@@ -1608,11 +1617,56 @@ int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int re
       best = p;
     }
   }
+  // the FP64 residual's load plan: one residual evaluation per candidate
+  for (int rl = 0; rl < 4; ++rl) {
+    usp_plan p = best;
+    p.r_load = rl;
+    op->plan = p;
+    double ms_min = INFINITY;
+    for (int rep = 0; rep < 3; ++rep) {
+      int r = 0;
+      HIPCHK(hipEventRecord(e0, op->st));
+      if (op->refine || op->dtype == USP_C128)
+        r = residual_passes<double2>(op, (double2*)x_dev, (const double2*)y_dev, (const double2*)op->B, nullptr,
+                                     nullptr);
+      else
+        r = residual_passes<float2>(op, (float2*)x_dev, (const float2*)y_dev, (const float2*)op->B, nullptr,
+                                    nullptr);
+      HIPCHK(hipEventRecord(e1, op->st));
+      HIPCHK(hipEventSynchronize(e1));
+      if (r) {
+        op->plan = saved;
+        return r;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      ms_min = std::min(ms_min, (double)ms);
+    }
+    if (rl == 0 || ms_min < best_ms) {
+      best_ms = ms_min;
+      best.r_load = rl;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   op->pending = op->pending_first = 0;
   op->plan = best;
   if (best_out) *best_out = best;
+  return 0;
+}
+
+int usp_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stream) {
+  if (!src_dev || !dst_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  if ((((uintptr_t)src_dev) | ((uintptr_t)dst_dev) | bytes) & 15)
+    return fail(USP_ERR_INVALID, "pointers and size must be multiples of 16 bytes");
+  const char *s = (const char*)src_dev, *d = (const char*)dst_dev;
+  if (s < d + bytes && d < s + bytes) return fail(USP_ERR_INVALID, "buffers overlap");
+  const long n = (long)(bytes / 16);
+  if (n == 0) return 0;
+  const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const double2*)src_dev,
+                     (double2*)dst_dev, n);
+  LAUNCHCHK("k_stream_copy");
   return 0;
 }
 

@@ -204,6 +204,23 @@ extern "C" int usp_canonical_diffusion(const double* mu_host, size_t n, double D
   return 0;
 }
 
+// Schrodinger operator shifted by Abar (Sec. 4, Eq. schrodinger; unit mass,
+// natural units): H + Abar = -1/2 laplacian + V + Abar is the constant-D
+// diffusion operator with D = 1/2, mu = V + Abar, omega = 0.  The smallest
+// circle of the real set {V + Abar} is centred at midrange(V) + Abar with the
+// radius of {V}, so c = (max V - min V)/(2 vnorm), the symbol's a0 is
+// midrange(V) + Abar, and B = 1 - (V - midrange(V))/c: the field bias returned
+// in bias_out is midrange(V), for usp_canonical_fields on V itself.
+extern "C" int usp_canonical_schrodinger(const double* V_host, size_t n, double shift, double vnorm,
+                                         const usp_symbol* grid, usp_symbol* sym_out, double* c_out,
+                                         double* bias_out) {
+  if (!std::isfinite(shift)) return USP_ERR_INVALID;
+  const int rc = usp_canonical_diffusion(V_host, n, 0.5, 0.0, vnorm, grid, sym_out, c_out, bias_out);
+  if (rc) return rc;
+  sym_out->a0[0] = bias_out[0] + shift;
+  return 0;
+}
+
 // Pantograph (Sec. 3.3, Eq. pantograph-A) on t_j = t0 + j h, j < n:
 //   A x = c^-1 [(d/dt + a) x + b x(lam t)],  y = c^-1 [b x0(lam t) + x0(t0) delta(t - t0)].
 // abar = smallest-circle centre of {a_j}; the dilation x(lam t_j) is a

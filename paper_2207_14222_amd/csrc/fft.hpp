@@ -41,6 +41,10 @@ template <class C> __device__ __forceinline__ C cmul(C a, C b) {
 template <class C> __device__ __forceinline__ C cconj(C a) { a.y = -a.y; return a; }
 template <class C> __device__ __forceinline__ C cscale(C a, typename real_of<C>::type s) { a.x *= s; a.y *= s; return a; }
 template <class C> __device__ __forceinline__ double cabs2(C a) { return (double)a.x * a.x + (double)a.y * a.y; }
+// |a|^2 in the precision of the field (FP32 for complex64, FP64 for complex128),
+// one explicit fused multiply-add so the rounding does not depend on how the
+// compiler schedules the surrounding code
+template <class C> __device__ __forceinline__ typename real_of<C>::type cnorm2(C a) { return fma(a.y, a.y, a.x * a.x); }
 
 // conversion between storage and compute precision
 template <class D, class S> __device__ __forceinline__ D cvt(S s) {
@@ -211,23 +215,24 @@ struct BlockSync {
 };
 
 // Reductions ----------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+// R is float (norms of complex64 iterations) or double (FP64 residuals).
+template <class R> __device__ __forceinline__ R wave_sum(R v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
-// Sum of one double per thread over the block; result valid in every thread.
-// `scratch` must hold 64 doubles (static LDS).  Deterministic: fixed shuffle
+// Sum of one value per thread over the block; result valid in every thread.
+// `scratch` must hold 64 values (static LDS).  Deterministic: fixed shuffle
 // tree inside each wave, waves added in index order.  Blocks smaller than one
 // wave add through LDS serially.
-__device__ __forceinline__ double block_sum(double v, double* scratch) {
+template <class R> __device__ __forceinline__ R block_sum(R v, R* scratch) {
   const int nt = blockDim.x;
   if (nt < 64) {
     __syncthreads();
     scratch[threadIdx.x] = v;
     __syncthreads();
-    double s = 0.0;
+    R s = R(0);
     for (int i = 0; i < nt; ++i) s += scratch[i];
     __syncthreads();
     return s;
@@ -238,7 +243,7 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   __syncthreads();
   if (lane == 0) scratch[wid] = v;
   __syncthreads();
-  double s = 0.0;
+  R s = R(0);
   for (int w = 0; w < nw; ++w) s += scratch[w];
   __syncthreads();
   return s;
@@ -248,8 +253,8 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
 // Rows are summed in block order by k_sum_rows in a later launch, so the result
 // is deterministic and no cross-block fence or atomic is needed (a device-scope
 // fence writes back the whole L2 on this chip).
-__device__ __forceinline__ void block_partial(double v, double* scratch, double* row) {
-  const double s = block_sum(v, scratch);
+template <class R> __device__ __forceinline__ void block_partial(R v, R* scratch, R* row) {
+  const R s = block_sum(v, scratch);
   if (row && threadIdx.x == 0) row[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = s;
 }
 

@@ -249,10 +249,16 @@ int fx_row(const FxRun& R, Cc* spec, Cx* x, const Cx* y, const Cx* bu, const Cx*
 }
 
 // ordered sums of `nrows` partial rows starting at ring row `first` into out
-int fx_sum(const FxRun& R, int first, int nrows, int ring, double* out, int out_first, int out_ring) {
+// (FP32 partials of complex64 iterations if f32)
+int fx_sum(const FxRun& R, int first, int nrows, int ring, double* out, int out_first, int out_ring,
+           bool f32 = false) {
   if (nrows <= 0) return 0;
-  hipLaunchKernelGGL(k_fx_sum<0>, dim3(nrows), dim3(256), 0, R.st, R.part(), R.L.pitch, (int)R.L.pitch, first, ring,
-                     out, out_first, out_ring);
+  if (f32)
+    hipLaunchKernelGGL(k_fx_sum<float>, dim3(nrows), dim3(256), 0, R.st, reinterpret_cast<const float*>(R.part()),
+                       2 * R.L.pitch, (int)R.L.pitch, first, ring, out, out_first, out_ring);
+  else
+    hipLaunchKernelGGL(k_fx_sum<double>, dim3(nrows), dim3(256), 0, R.st, R.part(), R.L.pitch, (int)R.L.pitch, first,
+                       ring, out, out_first, out_ring);
   LAUNCHCHK("k_fx_sum");
   return 0;
 }
@@ -282,6 +288,7 @@ struct FxHist {
   const FxRun& R;
   double* hist_pre;
   int hist_pre_cap;
+  bool f32;          // the rows hold complex64 iterations' FP32 partials
   int it = 0, pulled = 0, flushed = 0, grow = 0, status = USP_MAXIT;
   double d0 = -1.0, dprev = -1.0;
   double tail[16];   // latest values (ring), for the refined solve's rate
@@ -296,7 +303,7 @@ struct FxHist {
   // sum the pending partial rows of iterations [flushed, it) into the history ring
   int flush() {
     const int m = it - flushed;
-    const int e = fx_sum(R, flushed % kFxRows, m, kFxRows, R.hist(), flushed % kFxHist, kFxHist);
+    const int e = fx_sum(R, flushed % kFxRows, m, kFxRows, R.hist(), flushed % kFxHist, kFxHist, f32);
     flushed = it;
     return e;
   }
@@ -339,7 +346,7 @@ int fx_solve(const FxRun& R, const C* bu, const C* b2, const C* y, C* x, int x_i
   C* t = R.t<C>();
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * (R.d + 1) * R.N, R.st));
   if ((rc = fx_row<C, C, FX_FIRST>(R, t, x, y, bu, b2, 0.0, x_is_guess ? 1 : 0, nullptr, nullptr))) return rc;
-  FxHist H{R, hist_pre, hist_pre_cap};
+  FxHist H{R, hist_pre, hist_pre_cap, sizeof(C) == 8};
   int ntrue = 0;
   while (H.it < maxit) {
     if ((rc = fx_symbol<C>(R, t, true))) return rc;
@@ -386,7 +393,7 @@ int fx_solve_refined(const FxRun& R, const double2* bu, const double2* b2, const
   hipLaunchKernelGGL(k_fx_to32<0>, dim3(1024), dim3(256), 0, R.st, b2, b232, nb2);
   LAUNCHCHK("k_fx_to32");
   if (!x_is_guess) HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * (R.d + 1) * R.N, R.st));
-  FxHist H{R, hist_pre, hist_pre_cap};
+  FxHist H{R, hist_pre, hist_pre_cap, true};
   int ntrue = 0;
   bool judge = x_is_guess == 2;
   const float2* dcor = nullptr;

@@ -364,12 +364,12 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
 #pragma unroll
     for (int e = 0; e < E; ++e) z[e] = csub(a[e], xv[e]);
     exch(z, fl);
-    double acc = 0.0;
+    Rr acc = Rr(0);   // in the precision of the iteration
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const Cc dl = bapply(e, z[e], fl);
       xv[e] = cadd(xv[e], cscale(dl, al));
-      acc += cabs2(dl);
+      acc += cnorm2(dl);
     }
     if (act) {
 #pragma unroll
@@ -383,7 +383,8 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
 #pragma unroll
       for (int e = 0; e < E; ++e) spec[base + tt + T * e] = a[e];
     }
-    block_partial(acc, scratch, row0);
+    // complex64: FP32 partials at the start of the row
+    block_partial(acc, reinterpret_cast<Rr*>(scratch), reinterpret_cast<Rr*>(row0));
   } else {  // FX_RINV
     Cc xv[E], fl[D][E];
 #pragma unroll
@@ -418,16 +419,17 @@ __global__ void __launch_bounds__(256) k_fx_to32(const double2* __restrict__ in,
     out[i] = make_float2((float)in[i].x, (float)in[i].y);
 }
 
-// block i adds row (first + i) % ring of `part` (ncols partials each, pitch
-// apart) in a fixed order into out[(out_first + i) % out_ring]
-template <int U = 0>
-__global__ void __launch_bounds__(256) k_fx_sum(const double* __restrict__ part, long pitch, int ncols, int first,
+// block i adds row (first + i) % ring of `part` (ncols partials of type R
+// each, pitch elements of R apart) in a fixed order, in the precision of the
+// partials, into out[(out_first + i) % out_ring]
+template <class R>
+__global__ void __launch_bounds__(256) k_fx_sum(const R* __restrict__ part, long pitch, int ncols, int first,
                                                 int ring, double* __restrict__ out, int out_first, int out_ring) {
-  __shared__ double scratch[64];
-  const double* row = part + (long)((first + (int)blockIdx.x) % ring) * pitch;
-  double acc = 0.0;
+  __shared__ R scratch[64];
+  const R* row = part + (long)((first + (int)blockIdx.x) % ring) * pitch;
+  R acc = R(0);
   for (int i = threadIdx.x; i < ncols; i += blockDim.x) acc += row[i];
-  const double s = block_sum(acc, scratch);
+  const R s = block_sum(acc, scratch);
   if (threadIdx.x == 0) out[(out_first + (int)blockIdx.x) % out_ring] = s;
 }
 

@@ -99,6 +99,10 @@ inline int make_layout(const usp_symbol* L, int dtype, int flags, Layout* lay, D
   const bool antisym = (flags & USP_FLAG_ANTISYM) != 0;
   if (antisym && (dims->ndim != 1 || refine)) return fail(USP_ERR_INVALID, "the antisymmetrised form is for 1-D handles");
   if (flags & ~(USP_FLAG_REFINE | USP_FLAG_ANTISYM)) return fail(USP_ERR_INVALID, "unknown flag");
+  // the first-derivative term and its Nyquist convention exist for 1-D symbols
+  // only: the multi-axis passes apply c0 + c2 |p|^2
+  if (dims->ndim >= 2 && (L->a1[0] != 0.0 || L->a1[1] != 0.0 || L->nyquist_zero))
+    return fail(USP_ERR_INVALID, "a1 and nyquist_zero must be 0 for 2-D and 3-D symbols");
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -160,6 +164,7 @@ struct usp_op_s {
   long pitch = 0;          // row pitch of partials (doubles)
   int pending = 0;         // per-iteration rows written since the last finalisation
   int pending_first = 0;   // iteration index of the first pending row
+  bool pending_f32 = false;  // the pending rows hold complex64 iterations' FP32 partials
   int xblocks = 0;         // blocks of the last complex64/128 contiguous-axis launch (row width)
   double* hist = nullptr;
   double* scal = nullptr;

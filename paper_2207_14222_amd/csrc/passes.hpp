@@ -26,7 +26,8 @@ enum XMode { X_FIRST = 0, X_FUSED = 1, X_RFWD = 2, X_RINV = 3 };
 enum SMode { S_FWD = 0, S_INV = 1, S_SYM = 2, S_SYMA = 3 };
 
 struct RedArgs {
-  double* row;  // per-block partial sums of this launch (NULL: none)
+  double* row;  // per-block partial sums of this launch (NULL: none); a launch
+                // in complex64 writes them as floats at the start of the row
 };
 
 template <class C> constexpr int x_threads() { return sizeof(C) == 8 ? 256 : 128; }
@@ -98,14 +99,14 @@ template <int N, class P> __device__ __forceinline__ void idle_fft_syncs() {
 // type of x, y, B.  Body for LPB lines starting at line0 (TH = LPB*T
 // threads take part; threads >= TH only join the barriers and must form whole
 // waves).  tws: twiddles in LDS; lds: LPB padded rows.  Returns the thread's
-// partial sum of |Delta|^2 (X_FUSED) or |r|^2 (X_RINV).
+// partial sum of |Delta|^2 (X_FUSED, in the precision of Cc) or |r|^2 (X_RINV).
 // FL (fused pass only): bit 0 = load x, B, y before the inverse FFT;
 // bit 1 = stream x, B, y (non-temporal loads / store).
 // TL (X_FIRST / X_FUSED): 0 = t row-major like x; TL > 0 = t in column tiles
 // of width TL, element (line, pos) at ((pos / TL) nlines + line) TL + pos % TL,
 // so that the strided pass reads each tile as one contiguous block.
 template <class Cc, class Cx, int N, int MODE, int FL, int LPB, int TL = 0>
-__device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y,
+__device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y,
                                              const Cx* __restrict__ B, const float2* __restrict__ d,
                                              float2* __restrict__ r32, const Cc* tws, Cc* lds, double alpha,
                                              long line0, long nlines, int has_x) {
@@ -122,7 +123,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
     } else {
       idle_fft_syncs<N, typename PP::P>();
     }
-    return 0.0;
+    return Rr(0);
   }
   const int tt = tid % T, li = tid / T;
   const long line = line0 + li;
@@ -130,7 +131,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
   const long base = line * N;
   LdsRow<Cc> row{lds + li * PADN};
   Cc v[E];
-  double acc = 0.0;
+  Rr acc = Rr(0);
   auto tix = [&](int pos) -> long {
     return TL ? ((long)(pos / TL) * nlines + line) * TL + pos % TL : base + pos;
   };
@@ -152,7 +153,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
 #pragma unroll
       for (int e = 0; e < E; ++e) t[tix(tt + T * e)] = v[e];
     }
-    return 0.0;
+    return Rr(0);
   }
 
   if (MODE == X_FUSED) {
@@ -185,7 +186,7 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
     for (int e = 0; e < E; ++e) {
       const Cc dl = cmul(bb[e], csub(v[e], xx[e]));     // Delta = B (u - x)
       const Cc xn = cadd(xx[e], cscale(dl, a));         // x + alpha Delta
-      acc += cabs2(dl);
+      acc += cnorm2(dl);
       if (active) st<NT>(x + base + tt + T * e, cvt<Cx>(xn));
       v[e] = cadd(cmul(bb[e], xn), yy[e]);              // next t = B x + y
     }
@@ -216,24 +217,43 @@ __device__ __forceinline__ double xpass_body(Cc* __restrict__ t, Cx* __restrict_
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
     }
-    return 0.0;
+    return Rr(0);
   }
 
-  // X_RINV
+  // X_RINV.  FL bit 0: x, B, y loaded before the inverse FFT (their latency
+  // overlaps it); bit 1: non-temporal loads.
+  {
+    constexpr bool PF = (FL & 1) != 0, NT = (FL & 2) != 0;
+    Cc xx[E], bb[E], yy[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = active ? t[base + tt + T * e] : mk<Cc>(0.0, 0.0);
-  FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    if (active) {
+    for (int e = 0; e < E; ++e) {
       const long p = base + tt + T * e;
-      const Cc xx = cvt<Cc>(x[p]);
-      const Cc bb = cvt<Cc>(B[p]);
-      const Cc yy = cvt<Cc>(y[p]);
-      // r = y - L x - (1 - B) x
-      const Cc r = cadd(csub(csub(yy, v[e]), xx), cmul(bb, xx));
-      acc += cabs2(r);
-      if (r32) r32[p] = cvt<float2>(r);
+      v[e] = active ? t[p] : mk<Cc>(0.0, 0.0);
+      if (PF) {
+        xx[e] = active ? cvt<Cc>(ld<NT>(x + p)) : mk<Cc>(0.0, 0.0);
+        bb[e] = active ? cvt<Cc>(ld<NT>(B + p)) : mk<Cc>(0.0, 0.0);
+        yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
+      }
+    }
+    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    if (!PF) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const long p = base + tt + T * e;
+        xx[e] = active ? cvt<Cc>(ld<NT>(x + p)) : mk<Cc>(0.0, 0.0);
+        bb[e] = active ? cvt<Cc>(ld<NT>(B + p)) : mk<Cc>(0.0, 0.0);
+        yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      // r = y - L x - (1 - B) x, rounded in a fixed sequence (explicit fused
+      // multiply-adds) so that every load plan gives the same bits
+      Cc r;
+      r.x = fma(bb[e].x, xx[e].x, fma(-bb[e].y, xx[e].y, (yy[e].x - v[e].x) - xx[e].x));
+      r.y = fma(bb[e].x, xx[e].y, fma(bb[e].y, xx[e].x, (yy[e].y - v[e].y) - xx[e].y));
+      acc += cnorm2(r);
+      if (active && r32) r32[base + tt + T * e] = cvt<float2>(r);
     }
   }
   return acc;
@@ -247,12 +267,13 @@ k_xpass(Cc* __restrict__ t, Cx* __restrict__ x, const Cx* __restrict__ y, const 
   constexpr int T = N / PassPlan<N>::E;
   constexpr int LPB = (x_threads<Cc>() / T) > 0 ? (x_threads<Cc>() / T) : 1;
   __shared__ Cc lds[LPB * LdsRow<Cc>::padded(N)];
+  using Rr = typename real_of<Cc>::type;
   __shared__ Cc tws[N];
-  __shared__ double scratch[64];
+  __shared__ Rr scratch[64];
   load_twiddles<Cc, N>(tws, tw);
-  const double acc = xpass_body<Cc, Cx, N, MODE, FL, LPB>(t, x, y, B, d, r32, tws, lds, alpha,
-                                                         (long)blockIdx.x * LPB, nlines, has_x);
-  if (MODE == X_FUSED || MODE == X_RINV) block_partial(acc, scratch, red.row);
+  const Rr acc = xpass_body<Cc, Cx, N, MODE, FL, LPB>(t, x, y, B, d, r32, tws, lds, alpha,
+                                                     (long)blockIdx.x * LPB, nlines, has_x);
+  if (MODE == X_FUSED || MODE == X_RINV) block_partial(acc, scratch, reinterpret_cast<Rr*>(red.row));
 }
 
 // Strided-axis pass over a tile of W adjacent columns.  Element (pos, col, b)

@@ -32,15 +32,17 @@ __global__ void __launch_bounds__(256) k_norm2(const C* __restrict__ z, long n, 
   block_partial(acc, scratch, row);
 }
 
-// Block r adds row r of `part` (ncols partials, row pitch `pitch`) in a fixed
-// order and writes out[(first + r) % nmod].
-__global__ void __launch_bounds__(256) k_sum_rows(const double* __restrict__ part, long pitch, int ncols,
+// Block r adds row r of `part` (ncols partials of type R, row pitch `pitch`
+// elements of R) in a fixed order, in the precision of the partials, and
+// writes out[(first + r) % nmod].
+template <class R>
+__global__ void __launch_bounds__(256) k_sum_rows(const R* __restrict__ part, long pitch, int ncols,
                                                   double* __restrict__ out, int first, int nmod) {
-  __shared__ double scratch[64];
-  const double* row = part + (long)blockIdx.x * pitch;
-  double acc = 0.0;
+  __shared__ R scratch[64];
+  const R* row = part + (long)blockIdx.x * pitch;
+  R acc = R(0);
   for (int i = threadIdx.x; i < ncols; i += blockDim.x) acc += row[i];
-  const double s = block_sum(acc, scratch);
+  const R s = block_sum(acc, scratch);
   if (threadIdx.x == 0) out[(first + (int)blockIdx.x) % nmod] = s;
 }
 
@@ -73,6 +75,25 @@ __global__ void __launch_bounds__(256) k_max_final(const double* __restrict__ pa
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = sqrt(s[0]);
+}
+
+// dst = src in 16-byte units, non-temporal, four units in flight per thread
+__global__ void __launch_bounds__(256) k_stream_copy(const double2* __restrict__ src, double2* __restrict__ dst,
+                                                     long n) {
+  typedef double d2v __attribute__((ext_vector_type(2)));
+  const d2v* s = reinterpret_cast<const d2v*>(src);
+  d2v* d = reinterpret_cast<d2v*>(dst);
+  const long stride = (long)gridDim.x * blockDim.x;
+  long i = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const d2v a = __builtin_nontemporal_load(s + i), b = __builtin_nontemporal_load(s + i + stride);
+    const d2v c = __builtin_nontemporal_load(s + i + 2 * stride), e = __builtin_nontemporal_load(s + i + 3 * stride);
+    __builtin_nontemporal_store(a, d + i);
+    __builtin_nontemporal_store(b, d + i + stride);
+    __builtin_nontemporal_store(c, d + i + 2 * stride);
+    __builtin_nontemporal_store(e, d + i + 3 * stride);
+  }
+  for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + i), d + i);
 }
 
 // complex128 -> complex64

@@ -139,10 +139,19 @@ def canonical_diffusion(mu_a, D, omega_over_v, source, spacing, vnorm: float = 0
 def canonical_schrodinger(V, spacing, shift, vnorm: float = 0.95, dtype=torch.complex128,
                           device="cuda") -> Canonical:
     """H + shift = -1/2 laplacian + V + shift as the constant-D operator with D = 1/2,
-    mu = V + shift, omega = 0 (Sec. 4, Eq. schrodinger); energies E = c lam - shift."""
-    V = np.asarray(V, dtype=np.float64)
-    return canonical_diffusion(V + shift, 0.5, 0.0, np.zeros(V.shape), spacing, vnorm=vnorm, dtype=dtype,
-                               device=device)
+    mu = V + shift, omega = 0 (Sec. 4, Eq. schrodinger; usp_canonical_schrodinger +
+    usp_canonical_fields on V); energies E = c lam - shift."""
+    Vn = np.ascontiguousarray(np.asarray(V, dtype=np.float64))
+    grid = make_symbol(Vn.shape, spacing)
+    out = L.usp_symbol()
+    c = np.zeros(2)
+    b = np.zeros(2)
+    L.check(L.lib().usp_canonical_schrodinger(_dp(Vn.ravel()), Vn.size, float(shift), vnorm, ct.byref(grid),
+                                              ct.byref(out), _dp(c), _dp(b)))
+    q = torch.from_numpy(Vn.astype(np.complex128)).to(device)
+    S = torch.zeros(Vn.shape, dtype=torch.complex128, device=device)
+    Bt, yt = canonical_fields(q, S, complex(b[0], b[1]), complex(c[0], c[1]), 1.0, dtype)
+    return Canonical(out, Bt, yt, complex(c[0], c[1]), complex(b[0], b[1]))
 
 
 @dataclass
@@ -165,8 +174,10 @@ class CanonicalPantograph(Canonical):
 
 
 def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm: float = 0.95, dtype=torch.complex128,
-                         device="cuda") -> CanonicalPantograph:
-    """Pantograph canonical form (usp_canonical_pantograph, host) uploaded to the device."""
+                         device="cuda", nyquist_zero: bool = True) -> CanonicalPantograph:
+    """Pantograph canonical form (usp_canonical_pantograph, host) uploaded to the device.
+    nyquist_zero=False keeps the Nyquist mode of the derivative symbol (the choice the
+    antisymmetrised form needs; the library returns it set)."""
     def c128(z):
         return np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
     a, b, x0l = c128(a), c128(b), c128(x0_at_lam_t)
@@ -185,6 +196,7 @@ def canonical_pantograph(a, b, lam, t0, h, x0_at_lam_t, x0_t0, vnorm: float = 0.
                                              float(vnorm), ct.byref(sym), f(Bh),
                                              idx.ctypes.data_as(ct.POINTER(ct.c_int32)), f(g0), f(g1), f(yh),
                                              _dp(c), _dp(bias)))
+    sym.nyquist_zero = int(bool(nyquist_zero))
     T = lambda z: torch.from_numpy(z).to(device=device, dtype=dtype)
     return CanonicalPantograph(symbol=sym, B=T(Bh), y=T(yh), c=complex(c[0], c[1]), bias=complex(bias[0], bias[1]),
                                gather=(torch.from_numpy(idx).to(device), T(g0), T(g1)))
@@ -298,10 +310,11 @@ class Operator:
     def get_plan(self) -> dict:
         p = L.usp_plan()
         L.check(L.lib().usp_get_plan(self.handle, ct.byref(p)))
-        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream}
+        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream,
+                "r_load": p.r_load}
 
-    def set_plan(self, x_prefetch=0, w_mid=0, w_sym=0, x_stream=0):
-        p = L.usp_plan(int(x_prefetch), int(w_mid), int(w_sym), int(x_stream))
+    def set_plan(self, x_prefetch=0, w_mid=0, w_sym=0, x_stream=0, r_load=0):
+        p = L.usp_plan(int(x_prefetch), int(w_mid), int(w_sym), int(x_stream), int(r_load))
         L.check(L.lib().usp_set_plan(self.handle, ct.byref(p)))
 
     def autotune(self, y, x, alpha=0.8, reps=5) -> dict:
@@ -309,7 +322,8 @@ class Operator:
         p = L.usp_plan()
         L.check(L.lib().usp_autotune(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), float(alpha),
                                      int(reps), ct.byref(p)))
-        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream}
+        return {"x_prefetch": p.x_prefetch, "w_mid": p.w_mid, "w_sym": p.w_sym, "x_stream": p.x_stream,
+                "r_load": p.r_load}
 
     def krylov(self, y, x=None, method="bicgstab", restart=20, tol=1e-6, maxit=10000, check_every=20,
                hist_cap=None) -> SolveResult:
@@ -371,6 +385,17 @@ class Operator:
         L.check(L.lib().usp_residual(self.handle, _ptr(self._field(y)), _ptr(self._field(x)), _dp(rel), _dp(rn),
                                      _dp(yn)))
         return float(rel[0]), float(rn[0]), float(yn[0])
+
+
+def stream_copy(src: torch.Tensor, dst: torch.Tensor):
+    """usp_stream_copy: dst <- src (same byte size, contiguous device tensors) with
+    non-temporal loads and stores on the current stream (measurement hook)."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("contiguous device tensors expected")
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("src and dst must have the same size in bytes")
+    L.check(L.lib().usp_stream_copy(_ptr(src), _ptr(dst), nb, _stream_ptr(src.device)))
 
 
 def hermitian_eig(a):
@@ -510,6 +535,11 @@ class Batch:
     def __init__(self, ops, ys, xs, alpha=0.8, tol=1e-6, maxit=20000):
         if not (len(ops) == len(ys) == len(xs)) or not ops:
             raise ValueError("ops, ys, xs must have the same non-zero length")
+        for op, y, x in zip(ops, ys, xs):
+            if not op.flags & L.USP_FLAG_REFINE or op.dtype != torch.complex128:
+                raise ValueError("batched problems need refined complex128 operators")
+            op._field(y)
+            op._field(x)
         self.ops, self.ys, self.xs = ops, ys, xs
         self.n = len(ops)
         arr = (L.usp_batch_item * self.n)()

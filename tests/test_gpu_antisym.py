@@ -1,9 +1,12 @@
 """GPU parity of the antisymmetrised canonical form (1-D single-workgroup
 kernel, through the C ABI) against the FP64 oracle, on the pantograph.
 
-* non-accretive case (lam = 0.9, a = 0.1, b = -5): fixed-K iterates and the
-  residual against the oracle (complex128 1e-11, complex64 3e-5), ||Delta||
-  non-increasing, while the direct form diverges on the GPU as in the oracle;
+* non-accretive case (lam = 0.9, a = 0.1, b = -5; derivative symbol with the
+  Nyquist mode kept): fixed-K iterates and the residual against the oracle
+  (complex128 1e-11, complex64 3e-5), ||Delta|| non-increasing, while the
+  direct form diverges on the GPU as in the oracle; on the 256-sample window
+  the solve reaches 1e-8 at the oracle's iteration count (131 at alpha 0.8,
+  the behaviour Sec. 3.3 reports);
 * accretive case (lam = 0.5, b = 5): the antisymmetrised solve reaches the
   dense-LU solution of the original system in its first component, and
   zero in the second."""
@@ -26,11 +29,13 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def _build(pp, dtype=torch.complex128):
+def _build(pp, dtype=torch.complex128, nyquist_zero=False):
     from paper_2207_14222_amd import solver
-    cp = canon.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0)
+    cp = canon.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0,
+                                    nyquist_zero=nyquist_zero)
     aop = AS.AntisymOperator(operators.Operator(cp))
-    can = solver.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0, dtype=dtype)
+    can = solver.canonical_pantograph(pp.a, pp.b, pp.lam, pp.t0, pp.h, pp.x0_at_lam_t, pp.x0_t0, dtype=dtype,
+                                      nyquist_zero=nyquist_zero)
     op = solver.Operator(can.symbol, can.B, gather=can.gather, antisym=True)
     y = torch.stack([torch.zeros_like(can.y), can.y]).contiguous()
     return cp, aop, can, op, y
@@ -69,11 +74,34 @@ def test_direct_form_diverges_where_antisymmetrised_converges_monotonically():
     assert np.all(np.diff(d) <= 1e-12 * d[0]) and d[-1] < d[0]
 
 
+def test_nonaccretive_solve_count_and_solution():
+    """256-sample window, alpha 0.8, true residual checked every iteration: the GPU
+    stops at the oracle's count (below 150), its iterate there equals the oracle's,
+    and the first component is the original system's LU solution."""
+    _need_gpu()
+    print("[gpu-case] antisym solve n=256 non-accretive", flush=True)
+    pp = media.pantograph_constant(n=256)
+    cp, aop, can, op, y = _build(pp)
+    yo = AS.rhs(cp.y)
+    ref = R.solve(aop, yo, 0.8, 1e-8, 1000, 1)
+    res = op.solve(y, alpha=0.8, tol=1e-8, maxit=1000, check_every=1)
+    assert res.converged and ref.converged
+    assert abs(res.iterations - ref.iterations) <= 1 and res.iterations <= 150
+    xk, _ = R.iterate(aop, yo, 0.8, res.iterations)
+    assert rel(to_np(res.x), xk) < 1e-10
+    res2 = op.solve(y, alpha=0.8, tol=1e-13, maxit=5000, check_every=1)
+    assert res2.converged
+    x = to_np(res2.x)
+    xs = np.linalg.solve(operators.Operator(cp).dense_A(), cp.y)
+    assert rel(x[0], xs) < 1e-10
+    assert np.linalg.norm(x[1]) < 1e-10 * np.linalg.norm(xs)
+
+
 def test_accretive_pantograph_solution():
     _need_gpu()
     print("[gpu-case] antisym solve n=1024 accretive", flush=True)
     pp = media.pantograph(n=1024, b_value=5.0)
-    cp, aop, can, op, y = _build(pp)
+    cp, aop, can, op, y = _build(pp, nyquist_zero=True)
     res = op.solve(y, alpha=1.0, tol=1e-9, maxit=200000, check_every=100)
     assert res.converged, res.status_name
     x = to_np(res.x)

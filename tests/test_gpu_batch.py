@@ -127,3 +127,24 @@ def test_batched_1024_column_tiles_equal_single_solve():
                 assert torch.equal(a, r)
         for a, r in zip(runs[0][1], xref):
             assert rel(to_np(a), to_np(r)) < 1e-9
+
+
+def test_batch_rejects_fields_that_do_not_fit_the_operators():
+    """Batch checks dtype, shape, contiguity and device of every y and x before the
+    library sees a pointer (the kernels would read n^2 complex128 values)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2207_14222_amd import media, solver
+    p = media.helmholtz_disks(n=128, seed=4000)
+    can = solver.canonical_helmholtz(p.k2, p.source, p.spacing, dtype=torch.complex128)
+    op = solver.Operator(can.symbol, can.B, refine=True)
+    good = torch.zeros_like(can.y)
+    for bad in (good.to(torch.complex64), torch.zeros((128, 64), dtype=torch.complex128, device="cuda"),
+                torch.zeros((128, 256), dtype=torch.complex128, device="cuda")[:, ::2], good.cpu()):
+        with pytest.raises(ValueError):
+            solver.Batch([op], [can.y], [bad])
+        with pytest.raises(ValueError):
+            solver.Batch([op], [bad], [good])
+    plain = solver.Operator(can.symbol, can.B)
+    with pytest.raises(ValueError):
+        solver.Batch([plain], [can.y], [good])
