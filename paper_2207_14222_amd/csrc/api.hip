@@ -1663,9 +1663,11 @@ int usp_stream_copy(const void* src_dev, void* dst_dev, size_t bytes, void* stre
   if (s < d + bytes && d < s + bytes) return fail(USP_ERR_INVALID, "buffers overlap");
   const long n = (long)(bytes / 16);
   if (n == 0) return 0;
-  const int blocks = (int)std::min<long>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_stream_copy, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (const double2*)src_dev,
-                     (double2*)dst_dev, n);
+  const long chunk = 256L * kCopyUnroll;
+  const long blocks = (n + chunk - 1) / chunk;
+  if (blocks > 0x7fffffffL) return fail(USP_ERR_INVALID, "copy too large");
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     (const double2*)src_dev, (double2*)dst_dev, n);
   LAUNCHCHK("k_stream_copy");
   return 0;
 }
