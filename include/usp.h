@@ -209,6 +209,23 @@ int usp_set_plan(usp_op op, const usp_plan* plan);
  * of all candidates are identical, so tuning never changes a solution. */
 int usp_autotune(usp_op op, const void* y_dev, void* x_dev, double alpha, int reps, usp_plan* best_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * true residual of usp_residual computed without an operator handle or a
+ * workspace, every temporary (twiddle tables, partial sums, the FP64 spectrum)
+ * in a static device array of USP_STATIC_SCRATCH_BYTES that each GPU holds
+ * until the process ends.  L: the symbol (as for usp_prepare_operator; no
+ * gather term), dtype USP_C64 or USP_C128 for B_dev, y_dev, x_dev (device,
+ * contiguous, C order, caller-owned).  Outputs as usp_residual.  Grids whose
+ * temporaries exceed the array (2-D / 3-D: about 16 bytes per point plus
+ * partial rows; 128^3 fits, 256^3 does not): USP_ERR_WORKSPACE.  Runs on
+ * `stream`, which must belong to the current device, and synchronises it.
+ * Allocates nothing: no hipMalloc, hipFree or allocating library call.
+ * Calls that overlap on one GPU share its array and race; serialise them. */
+#define USP_STATIC_SCRATCH_BYTES (64 * 1024 * 1024)
+int usp_residual_static(const usp_symbol* L, int dtype, const void* B_dev, const void* y_dev, const void* x_dev,
+                        double* rel_out, double* rnorm_out, double* ynorm_out, void* stream);
+
 /* Measurement hook (not part of the method): copy `bytes` bytes from src_dev
  * to dst_dev on `stream` with non-temporal 16-byte loads and stores, the
  * streaming ceiling that the pass kernels' HBM rates are compared with.  Both

@@ -35,7 +35,7 @@ EXPORTS = ["usp_workspace_bytes", "usp_prepare_operator", "usp_solve", "usp_iter
            "usp_canonical_flux", "usp_flux_workspace_bytes", "usp_flux_solve", "usp_flux_residual",
            "usp_flux_refined_workspace_bytes", "usp_flux_solve_refined",
            "usp_eigs_workspace_bytes", "usp_eigs", "usp_hermitian_eig", "usp_stream_copy",
-           "usp_canonical_schrodinger"]
+           "usp_canonical_schrodinger", "usp_residual_static"]
 USP_NPASS = 11
 PASS_NAMES = ["x_fused", "m_fwd", "sym", "m_inv", "x_first", "r_fwd", "r_mfwd", "r_sym", "r_minv", "r_inv", "reduce"]
 
@@ -94,6 +94,7 @@ def lib():
     L.usp_solve.argtypes = [P, P, P, I, D, D, I, I, IP, DP, I, DP, I, IP]
     L.usp_iterate.argtypes = [P, P, P, I, D, I, DP, I]
     L.usp_residual.argtypes = [P, P, P, DP, DP, DP]
+    L.usp_residual_static.argtypes = [ct.POINTER(usp_symbol), I, P, P, P, DP, DP, DP, P]
     L.usp_destroy.argtypes = [P]
     L.usp_last_error.argtypes = []
     L.usp_last_error.restype = ct.c_char_p

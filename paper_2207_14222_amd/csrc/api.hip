@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <string>
 #include <type_traits>
@@ -1094,6 +1095,69 @@ void cmulh(const double a[2], const double b[2], double out[2]) {
 
 }  // namespace
 
+// ---- static device scratch (callers that cannot allocate device memory) ----
+//
+// usp_residual_static keeps everything it needs besides its inputs in this
+// array: the twiddle tables of every length 8 .. 1024 (written once per
+// device), the per-block partial rows, two scalars and the FP64 spectrum of
+// A x.  Each GPU the library runs on holds its own copy until the process
+// ends.  In host code `scratch` only stands in for the symbol: its device
+// address, different on every GPU, comes from hipGetSymbolAddress with that
+// device current and is the only pointer passed to kernels.
+static __device__ __align__(256) char scratch[USP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kTwdBytes = sizeof(double2) * 2040;   // lengths 8 .. 1024: sum = 2040 entries
+constexpr size_t kTwfBytes = sizeof(float2) * 2040;
+constexpr size_t kTwRegion = 49152;                    // both tables, 256-byte aligned
+static_assert(kTwdBytes + kTwfBytes <= kTwRegion, "twiddle region");
+
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxDevices] = {nullptr};
+
+// offset of the length-n table (n = 2^l, 3 <= l <= 10) in entries: 8 + 16 + ... + n/2 = n - 8
+inline size_t tw_entry(int n) { return (size_t)n - 8; }
+
+// the current device's scratch address; on the first call for a device its
+// address is looked up and the twiddle tables exp(-2 pi i k / n), computed in
+// long double, are copied in
+int static_scratch(char** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(USP_ERR_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(USP_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    static double2 td[2040];
+    static float2 tf[2040];
+    for (int l = 3; l <= 10; ++l) {
+      const int n = 1 << l;
+      for (int k = 0; k < n; ++k) {
+        const long double a = -2.0L * 3.141592653589793238462643383279502884L * (long double)k / (long double)n;
+        const long double c = cosl(a), sn = sinl(a);
+        td[tw_entry(n) + k].x = (double)c;
+        td[tw_entry(n) + k].y = (double)sn;
+        tf[tw_entry(n) + k].x = (float)c;
+        tf[tw_entry(n) + k].y = (float)sn;
+      }
+    }
+    char* base = (char*)p;
+    if (hipMemcpy(base, td, kTwdBytes, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + kTwdBytes, tf, kTwfBytes, hipMemcpyHostToDevice) != hipSuccess)
+      return fail(USP_ERR_HIP, "twiddle upload to the static scratch failed");
+    g_scratch_dev[dev] = base;
+  }
+  *out = g_scratch_dev[dev];
+  return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* usp_last_error(void) { return g_err.c_str(); }
@@ -1541,6 +1605,66 @@ int usp_profile(usp_op op, const void* y_dev, void* x_dev, double alpha, int K, 
     if (r) return r;
     *iter_ms = ms / K;
   }
+  return 0;
+}
+
+int usp_residual_static(const usp_symbol* L, int dtype, const void* B_dev, const void* y_dev, const void* x_dev,
+                        double* rel_out, double* rnorm_out, double* ynorm_out, void* stream) {
+  if (!L || !B_dev || !y_dev || !x_dev) return fail(USP_ERR_INVALID, "NULL argument");
+  Layout lay;
+  Dims d;
+  int rc = make_layout(L, dtype, 0, &lay, &d);   // validates the symbol and dtype
+  if (rc) return rc;
+  // scratch: twiddles | scalars | partial rows | FP64 spectrum (2-D / 3-D)
+  const long nblk = (long)d.n0 * d.n1 + 4096;
+  const size_t off_scal = kTwRegion;
+  const size_t off_part = align_up(off_scal + 64 * sizeof(double));
+  const size_t off_S = align_up(off_part + sizeof(double) * nblk * (kRows + 2));
+  const size_t need = d.ndim >= 2 ? align_up(off_S + (size_t)d.N * 16) : off_S;
+  if (need > (size_t)USP_STATIC_SCRATCH_BYTES)
+    return fail(USP_ERR_WORKSPACE, "grid too large for the static scratch: needs " + std::to_string(need) +
+                                       " bytes of " + std::to_string((size_t)USP_STATIC_SCRATCH_BYTES));
+  char* base = nullptr;
+  if ((rc = static_scratch(&base))) return rc;
+  // an operator record on the stack over the scratch (no allocation)
+  usp_op_s o;
+  o.d = d;
+  o.dtype = dtype;
+  o.st = (hipStream_t)stream;
+  o.sym = *L;
+  o.B = B_dev;
+  o.S = d.ndim >= 2 ? (double2*)(base + off_S) : nullptr;
+  o.partials = (double*)(base + off_part);
+  o.pitch = nblk;
+  o.scal = (double*)(base + off_scal);
+  for (int l = 3; l <= 10; ++l) {
+    o.twd[l] = (double2*)base + tw_entry(1 << l);
+    o.twf[l] = (float2*)(base + kTwdBytes) + tw_entry(1 << l);
+  }
+  cmulh(L->s, L->a0, o.sa0);
+  cmulh(L->s, L->a1, o.sa1);
+  cmulh(L->s, L->a2, o.sa2);
+  double host[2];
+  if (d.ndim == 1) {
+    rc = dtype == USP_C64 ? residual_1d<float2>(&o, (const float2*)y_dev, (const float2*)x_dev, host)
+                          : residual_1d<double2>(&o, (const double2*)y_dev, (const double2*)x_dev, host);
+    if (rc) return rc;
+  } else {
+    if (dtype == USP_C64) {
+      if ((rc = norm2(&o, (const float2*)y_dev, o.scal + 1))) return rc;
+      rc = residual_passes<float2>(&o, (float2*)x_dev, (const float2*)y_dev, (const float2*)B_dev, nullptr, nullptr);
+    } else {
+      if ((rc = norm2(&o, (const double2*)y_dev, o.scal + 1))) return rc;
+      rc = residual_passes<double2>(&o, (double2*)x_dev, (const double2*)y_dev, (const double2*)B_dev, nullptr,
+                                    nullptr);
+    }
+    if (rc) return rc;
+    HIPCHK(hipMemcpyAsync(host, o.scal, 2 * sizeof(double), hipMemcpyDeviceToHost, o.st));
+    HIPCHK(hipStreamSynchronize(o.st));
+  }
+  if (rel_out) *rel_out = std::sqrt(host[0] / host[1]);
+  if (rnorm_out) *rnorm_out = std::sqrt(host[0]);
+  if (ynorm_out) *ynorm_out = std::sqrt(host[1]);
   return 0;
 }
 
