@@ -163,7 +163,7 @@ def bench_config1(args, log):
     return out
 
 
-def bench_batch(args, log):
+def bench_batch(args, log, sequential=True):
     """96 independent 2-D Helmholtz problems (sides drawn from {128, 256, 512, 1024},
     random disks, beam on row 20; seeds 4 / 4000+i) solved together by the autotuned
     batched schedule (grouped graph-captured launches in practice; complex64 + FP64
@@ -181,7 +181,10 @@ def bench_batch(args, log):
     log(f"batch: {len(sizes)} problems prepared")
     xs = [torch.zeros_like(c.y) for c in cans]
     b = solver.Batch(ops, [c.y for c in cans], xs, alpha=args.batch_alpha, tol=args.tol, maxit=20000)
-    variant = b.autotune(refine_every=args.batch_refine_every)
+    if args.batch_variant is None:
+        variant = b.autotune(refine_every=args.batch_refine_every)
+    else:
+        variant = b.variant = args.batch_variant
     b.solve(refine_every=args.batch_refine_every, use_graph=True)   # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -190,6 +193,10 @@ def bench_batch(args, log):
     wall = time.perf_counter() - t0
     sched = "one persistent launch" if variant & 4 else "grouped launches, one graph replay per refinement cycle"
     log(f"batch: {sched}: {out.elapsed_ms:.1f} ms device, {wall * 1e3:.1f} ms wall, variant {variant}")
+    if not sequential:
+        return {"n_problems": len(sizes), "variant": variant, "schedule": sched,
+                "aggregate_time_to_tol_ms": round(out.elapsed_ms, 3),
+                "all_converged": bool(all(st == 0 for st in out.status))}
     # one problem at a time
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -515,6 +522,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the plain complex128/complex64 reference solves")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch plan")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 2-D workload")
+    ap.add_argument("--batch-variant", type=int, default=None,
+                    help="batched schedule variant (bits 0-1 fused-pass plan, bit 2 persistent); default: autotuned")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="profiling aid: run only the batched workload's autotuned solve (no headline line)")
     ap.add_argument("--batch-n", type=int, default=96)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess workload")
     ap.add_argument("--no-flux", action="store_true", help="skip the flux-form tensor diffusion workload")
@@ -540,6 +551,11 @@ def main():
         sys.exit(2)
 
     from paper_2207_14222_amd import media, solver
+
+    if args.batch_only:
+        out = bench_batch(args, log, sequential=False)
+        print(json.dumps({"batched": out}), flush=True)
+        return
 
     shape = tuple(int(s) for s in args.shape.split(","))
     N = int(np.prod(shape))

@@ -272,7 +272,11 @@ int usp_batch_workspace_bytes(const usp_batch_item* items, int nprob, size_t* by
  *     active work shrinks by a quarter);
  *   4 persistent: ONE launch (captured in a hipGraph when use_graph = 1) in
  *     which each workgroup takes whole problems, largest first, from a ticket
- *     counter and solves them alone; workgroups never wait for each other.
+ *     counter and solves them alone; workgroups never wait for each other;
+ * bit 3 (grouped schedule only; variants 8-11): the column pass works on
+ * tiles half as wide (4 columns for 1024^2 problems, 8 for the others) in
+ * blocks of 256 threads instead of 512.  Every variant gives the same
+ * solution to rounding; variants 12-15 are invalid.
  * Graphs run on a private default-priority stream ordered after `stream`.
  * results (host, may be NULL; in item order) and elapsed_ms (device time) are
  * filled in.  Returns the worst status (errors < 0 first). */
@@ -281,7 +285,7 @@ int usp_solve_batched(const usp_batch_item* items, int nprob, int refine_every, 
                       double* elapsed_ms);
 
 /* Autotuner of the batched solve: runs 2 * refine_every iterations of every
- * problem with each variant (0..7) and returns the fastest (overwrites x_dev). */
+ * problem with each variant (0..11) and returns the fastest (overwrites x_dev). */
 int usp_autotune_batched(const usp_batch_item* items, int nprob, int refine_every, void* workspace_dev,
                          size_t workspace_bytes, void* stream, int* best_variant);
 

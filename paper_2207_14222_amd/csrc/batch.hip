@@ -1,6 +1,7 @@
 // Batched solve of many independent, uneven-size 2-D problems (host side).
 //
-// Two schedules (usp_solve_batched `variant` bit 2):
+// Two schedules (usp_solve_batched `variant` bit 2; bit 3 halves the column
+// tiles of the grouped schedule):
 //  * grouped (default): each launch covers the tiles of every active problem
 //    (group.hpp); a refinement cycle is FIRST, k x [SYM, FUSED], RFWD, SYMA,
 //    RINV, FINAL, with per-problem convergence, status and timestamps decided
@@ -29,9 +30,9 @@ int g_lpb_rt(int n) {
   with_n(n, [&](auto NC) { v = g_lpb<decltype(NC)::value>(); });
   return v;
 }
-int g_w64_rt(int n) {
+int g_w64_rt(int n, int nw) {
   int v = 0;
-  with_n(n, [&](auto NC) { v = g_w64<decltype(NC)::value>(); });
+  with_n(n, [&](auto NC) { v = nw ? g_w64<decltype(NC)::value, 1>() : g_w64<decltype(NC)::value, 0>(); });
   return v;
 }
 int g_w128_rt(int n) {
@@ -146,12 +147,12 @@ BatchProblem make_problem(const usp_batch_item& it, int k) {
 struct Tasks {
   std::vector<GTask> xt, s64, s128;
 };
-Tasks build_tasks(const std::vector<BatchProblem>& tab, const std::vector<char>& active) {
+Tasks build_tasks(const std::vector<BatchProblem>& tab, const std::vector<char>& active, int nw) {
   Tasks T;
   for (int p = 0; p < (int)tab.size(); ++p) {
     if (!active[p]) continue;
     const int n = tab[p].n;
-    const int lpb = g_lpb_rt(n), w64 = g_w64_rt(n), w128 = g_w128_rt(n);
+    const int lpb = g_lpb_rt(n), w64 = g_w64_rt(n, nw), w128 = g_w128_rt(n);
     int slot = 0;
     for (int l = 0; l < n; l += lpb) T.xt.push_back(GTask{p, l, slot++, 0});
     for (int c = 0; c < n; c += w64) T.s64.push_back(GTask{p, c, 0, 0});
@@ -160,16 +161,16 @@ Tasks build_tasks(const std::vector<BatchProblem>& tab, const std::vector<char>&
   return T;
 }
 
-template <int FL>
+template <int FL, int NW>
 int launch_inner_cycle(hipStream_t st, const BatchProblem* dtab, GState* dst, double* part, long pitch,
                        const GTask* xt, int nx, const GTask* s64, int ns64, const GTask* s128, int ns128,
                        const int* nslots, int nprob, int k) {
   // complex64 inner iterations on A d = r from d = 0
   // (problems whose cycle budget is below k skip the remaining launches)
-  hipLaunchKernelGGL((k_gx<1, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
+  hipLaunchKernelGGL((k_gx<1, 0, NW>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL((k_gs<0>), dim3(ns64), dim3(kGS64), 0, st, s64, dtab, dst, j);
-    hipLaunchKernelGGL((k_gx<2, FL>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, j);
+    hipLaunchKernelGGL((k_gs<0, NW>), dim3(ns64), dim3(kGS64 >> NW), 0, st, s64, dtab, dst, j);
+    hipLaunchKernelGGL((k_gx<2, FL, NW>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, j);
   }
   // FP64 residual of x + d (x += d) and the per-problem decision
   hipLaunchKernelGGL((k_gx<5, 0>), dim3(nx), dim3(kGX), 0, st, xt, dtab, dst, part, pitch, 0);
@@ -179,20 +180,28 @@ int launch_inner_cycle(hipStream_t st, const BatchProblem* dtab, GState* dst, do
   return 0;
 }
 
-int inner_cycle_fl(int fl, hipStream_t st, const BatchProblem* dtab, GState* dst, double* part, long pitch,
+int inner_cycle_fl(int fl, int nw, hipStream_t st, const BatchProblem* dtab, GState* dst, double* part, long pitch,
                    const GTask* xt, int nx, const GTask* s64, int ns64, const GTask* s128, int ns128,
                    const int* nslots, int nprob, int k) {
-  switch (fl) {
-    case 1: launch_inner_cycle<1>(st, dtab, dst, part, pitch, xt, nx, s64, ns64, s128, ns128, nslots, nprob, k); break;
-    case 2: launch_inner_cycle<2>(st, dtab, dst, part, pitch, xt, nx, s64, ns64, s128, ns128, nslots, nprob, k); break;
-    case 3: launch_inner_cycle<3>(st, dtab, dst, part, pitch, xt, nx, s64, ns64, s128, ns128, nslots, nprob, k); break;
-    default: launch_inner_cycle<0>(st, dtab, dst, part, pitch, xt, nx, s64, ns64, s128, ns128, nslots, nprob, k); break;
+#define USP_CYCLE(F, W) launch_inner_cycle<F, W>(st, dtab, dst, part, pitch, xt, nx, s64, ns64, s128, ns128, nslots, \
+                                                 nprob, k)
+  switch (fl + 4 * (nw ? 1 : 0)) {
+    case 1: USP_CYCLE(1, 0); break;
+    case 2: USP_CYCLE(2, 0); break;
+    case 3: USP_CYCLE(3, 0); break;
+    case 4: USP_CYCLE(0, 1); break;
+    case 5: USP_CYCLE(1, 1); break;
+    case 6: USP_CYCLE(2, 1); break;
+    case 7: USP_CYCLE(3, 1); break;
+    default: USP_CYCLE(0, 0); break;
   }
+#undef USP_CYCLE
   LAUNCHCHK("grouped cycle");
   return 0;
 }
 
-int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w, const BLayout& L, hipStream_t st,
+int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, int nw, char* w, const BLayout& L,
+                  hipStream_t st,
                   int use_graph, usp_batch_result* results, double* elapsed_ms, int clk_khz) {
   std::vector<BatchProblem> tab(nprob);
   for (int i = 0; i < nprob; ++i) tab[i] = make_problem(items[i], k);
@@ -209,7 +218,7 @@ int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w
     nslots[p] = (tab[p].n + lpb - 1) / lpb;  // tasks of the contiguous-axis passes
   }
   std::vector<char> active(nprob, 1);
-  Tasks T = build_tasks(tab, active);
+  Tasks T = build_tasks(tab, active, nw);
   HIPCHK(hipMemcpy(dtab, tab.data(), sizeof(BatchProblem) * nprob, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(dns, nslots.data(), sizeof(int) * nprob, hipMemcpyHostToDevice));
   auto upload = [&]() -> int {
@@ -254,7 +263,7 @@ int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w
     if (nact == 0 || cycles++ > max_cycles) break;
     const bool compact = !use_graph || !exec || active_x * 4 <= captured_x * 3;
     if (compact) {
-      T = build_tasks(tab, active);
+      T = build_tasks(tab, active, nw);
       if ((rc = upload())) break;
     }
     if (use_graph) {
@@ -264,7 +273,7 @@ int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w
         exec = nullptr;
         graph = nullptr;
         HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        rc = inner_cycle_fl(fl, cs, dtab, dst, part, L.pitch, dxt, (int)T.xt.size(), ds64, (int)T.s64.size(), ds128,
+        rc = inner_cycle_fl(fl, nw, cs, dtab, dst, part, L.pitch, dxt, (int)T.xt.size(), ds64, (int)T.s64.size(), ds128,
                             (int)T.s128.size(), dns, nprob, k);
         hipError_t ec = hipStreamEndCapture(cs, &graph);
         if (!rc && ec != hipSuccess) rc = fail(USP_ERR_HIP, std::string("capture: ") + hipGetErrorString(ec));
@@ -278,7 +287,7 @@ int solve_grouped(const usp_batch_item* items, int nprob, int k, int fl, char* w
         break;
       }
     } else {
-      if ((rc = inner_cycle_fl(fl, cs, dtab, dst, part, L.pitch, dxt, (int)T.xt.size(), ds64, (int)T.s64.size(),
+      if ((rc = inner_cycle_fl(fl, nw, cs, dtab, dst, part, L.pitch, dxt, (int)T.xt.size(), ds64, (int)T.s64.size(),
                                ds128, (int)T.s128.size(), dns, nprob, k)))
         break;
     }
@@ -408,8 +417,8 @@ int usp_batch_workspace_bytes(const usp_batch_item* items, int nprob, size_t* by
 
 int usp_solve_batched(const usp_batch_item* items, int nprob, int refine_every, int variant, void* ws,
                       size_t ws_bytes, void* stream, int use_graph, usp_batch_result* results, double* elapsed_ms) {
-  if (!items || nprob < 1 || !ws || refine_every < 1 || variant < 0 || variant > 7)
-    return fail(USP_ERR_INVALID, "invalid argument");
+  if (!items || nprob < 1 || !ws || refine_every < 1 || variant < 0 || variant > 15 || (variant & 12) == 12)
+    return fail(USP_ERR_INVALID, "invalid argument (variant 0..11 or 8..11 with bit 2 clear)");
   int rc = validate_items(items, nprob);
   if (rc) return rc;
   const BLayout L = batch_layout(items, nprob);
@@ -423,8 +432,8 @@ int usp_solve_batched(const usp_batch_item* items, int nprob, int refine_every, 
   if (variant & 4)
     return solve_persistent(items, nprob, refine_every, fl, (char*)ws, L, (hipStream_t)stream, use_graph, results,
                             elapsed_ms, clk_khz, ncu);
-  return solve_grouped(items, nprob, refine_every, fl, (char*)ws, L, (hipStream_t)stream, use_graph, results,
-                       elapsed_ms, clk_khz);
+  return solve_grouped(items, nprob, refine_every, fl, (variant >> 3) & 1, (char*)ws, L, (hipStream_t)stream,
+                       use_graph, results, elapsed_ms, clk_khz);
 }
 
 int usp_autotune_batched(const usp_batch_item* items, int nprob, int refine_every, void* ws, size_t ws_bytes,
@@ -438,7 +447,7 @@ int usp_autotune_batched(const usp_batch_item* items, int nprob, int refine_ever
   }
   double best = INFINITY;
   *best_variant = 0;
-  for (int v = 0; v < 8; ++v) {
+  for (int v = 0; v < 12; ++v) {   // grouped 0-3, persistent 4-7, grouped with narrow column tiles 8-11
     double ms = 0.0;
     int rc = usp_solve_batched(short_items.data(), nprob, refine_every, v, ws, ws_bytes, stream, 1, nullptr, &ms);
     if (rc < 0) return rc;

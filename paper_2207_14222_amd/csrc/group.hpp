@@ -37,11 +37,13 @@ constexpr int kGS64 = 512; // threads of the complex64 strided group kernel
 constexpr int kGS128 = 256;
 
 template <int N> constexpr int g_lpb() { return kGX / (N / PassPlan<N>::E); }
-template <int N> constexpr int g_w64() { return cmin(cmin(kGS64 / (N / PassPlan<N>::E), 16), N); }
+// NW = 1 (variant bit 3): column tiles half as wide, in blocks of kGS64 / 2
+// threads (more, smaller blocks per CU)
+template <int N, int NW = 0> constexpr int g_w64() { return cmin(cmin(kGS64 / (N / PassPlan<N>::E), 16), N) >> NW; }
 template <int N> constexpr int g_w128() { return cmin(cmin(kGS128 / (N / PassPlan<N>::E), 8), N); }
 // complex64 t of the 1024^2 problems is kept in column tiles of g_w64 (the
 // column pass reads 64 KB blocks instead of 64-byte row segments)
-template <int N> constexpr int g_tile() { return N == 1024 ? g_w64<N>() : 0; }
+template <int N, int NW = 0> constexpr int g_tile() { return N == 1024 ? g_w64<N, NW>() : 0; }
 
 template <class C> __device__ __forceinline__ void copy_tw(C* tws, const C* tw, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) tws[i] = tw[i];
@@ -51,7 +53,7 @@ template <class C> __device__ __forceinline__ void copy_tw(C* tws, const C* tw, 
 // GMODE: 0 init (B32, x = 0, |y|^2), 1 FIRST, 2 FUSED, 3 RFWD (first residual),
 // 4 RINV, 5 RFWD after inner iterations (x += d first).  j: index of a FUSED
 // launch within the cycle; problems whose cycle budget is spent skip it.
-template <int GMODE, int FL>
+template <int GMODE, int FL, int NW = 0>
 __global__ void __launch_bounds__(kGX)
 k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, const GState* __restrict__ st,
      double* __restrict__ part, long pitch, int j) {
@@ -92,11 +94,11 @@ k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
     } else {
       copy_tw(reinterpret_cast<float2*>(tws), P.twf, N);
       if (GMODE == 1) {
-        xpass_body<float2, float2, N, X_FIRST, 0, LPB, g_tile<N>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
+        xpass_body<float2, float2, N, X_FIRST, 0, LPB, g_tile<N, NW>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
                                                        reinterpret_cast<float2*>(tws), reinterpret_cast<float2*>(lds),
                                                        0.0, tk.start, N, 2);
       } else {
-        xpass_body<float2, float2, N, X_FUSED, FL, LPB, g_tile<N>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
+        xpass_body<float2, float2, N, X_FUSED, FL, LPB, g_tile<N, NW>()>(P.t, P.d32, P.r32, P.B32, nullptr, nullptr,
                                                         reinterpret_cast<float2*>(tws),
                                                         reinterpret_cast<float2*>(lds), P.alpha, tk.start, N, 1);
       }
@@ -121,12 +123,12 @@ k_gx(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
 
 // strided pass along axis 0 of every task's problem: SYM (complex64,
 // 1/(N (l + 1))) or SYMA (complex128, l(p)/N); j as in k_gx for SYM
-template <int GMODE>
-__global__ void __launch_bounds__(GMODE == 0 ? kGS64 : kGS128)
+template <int GMODE, int NW = 0>
+__global__ void __launch_bounds__(GMODE == 0 ? (kGS64 >> NW) : kGS128)
 k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, const GState* __restrict__ st, int j) {
   constexpr bool F64 = (GMODE == 1);
   using C = typename std::conditional<F64, double2, float2>::type;
-  constexpr int LDSN = F64 ? 1024 * 5 : 1024 * 9;
+  constexpr int LDSN = (F64 || NW) ? 1024 * 5 : 1024 * 9;
   __shared__ C lds[LDSN];
   __shared__ C tws[1024];
   // consecutive column tiles (which share cache lines when a tile row is
@@ -155,9 +157,10 @@ k_gs(const GTask* __restrict__ tasks, const BatchProblem* __restrict__ probs, co
       spass_body<double2, N, W, S_SYMA>(P.S, P.twd, reinterpret_cast<double2*>(tws),
                                         reinterpret_cast<double2*>(lds), N, sym, tk.start, 0);
     } else {
-      constexpr int W = g_w64<N>();
+      constexpr int W = g_w64<N, NW>();
       static_assert(N * (W + 1) <= LDSN, "LDS tile");
-      spass_body<float2, N, W, S_SYM, (g_tile<N>() > 0)>(P.t, P.twf, reinterpret_cast<float2*>(tws),
+      static_assert(W * (N / PassPlan<N>::E) <= (kGS64 >> NW), "block threads");
+      spass_body<float2, N, W, S_SYM, (g_tile<N, NW>() > 0)>(P.t, P.twf, reinterpret_cast<float2*>(tws),
                                                          reinterpret_cast<float2*>(lds), N, sym, tk.start, 0);
     }
   };

@@ -530,7 +530,8 @@ class BatchResult:
 class Batch:
     """Many independent square 2-D refined problems solved together (usp_solve_batched).
     ops: refined Operators; ys / xs: complex128 tensors.  variant: bits 0-1 fused-pass
-    plan, bit 2 persistent one-launch schedule (else grouped launches)."""
+    plan, bit 2 persistent one-launch schedule (else grouped launches), bit 3 narrow
+    column tiles of the grouped schedule."""
 
     def __init__(self, ops, ys, xs, alpha=0.8, tol=1e-6, maxit=20000):
         if not (len(ops) == len(ys) == len(xs)) or not ops:

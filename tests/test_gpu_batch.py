@@ -72,7 +72,7 @@ def test_batched_variants_and_graph_replays_identical():
     b = solver.Batch(ops, [c.y for c in cans], xs, alpha=0.8, tol=1e-8, maxit=3000)
     ref = b.solve(use_graph=False, variant=0)
     xref = [x.clone() for x in xs]
-    for v in (0, 1, 2, 3, 4, 7):
+    for v in (0, 1, 2, 3, 4, 7, 8, 11):
         outs = []
         for graph in (False, True, True):
             for x in xs:
@@ -88,14 +88,15 @@ def test_batched_variants_and_graph_replays_identical():
         for a, r in zip(outs[0][1], xref):
             assert rel(to_np(a), to_np(r)) < 1e-9
     best = b.autotune(refine_every=20)
-    assert 0 <= best <= 7
+    assert 0 <= best <= 11
 
 
 def test_batched_1024_column_tiles_equal_single_solve():
     """The grouped schedule keeps the complex64 spectrum of 1024^2 problems in
-    column tiles (a layout of its own); the solution must match the
-    single-problem refined solve (row-major spectrum), with every fused-pass
-    plan, and graph replays must reproduce the eager launch bit for bit."""
+    column tiles (a layout of its own, 8 or 4 columns wide); the solution must
+    match the single-problem refined solve (row-major spectrum), with every
+    fused-pass plan and both column-tile widths, and graph replays must
+    reproduce the eager launch bit for bit."""
     _need_gpu()
     from paper_2207_14222_amd import solver
     sizes = [1024, 64, 512]
@@ -112,7 +113,7 @@ def test_batched_1024_column_tiles_equal_single_solve():
         assert abs(out.iterations[i] - single.iterations) <= 60
         assert rel(to_np(xs[i]), to_np(single.x)) < 1e-8, i
         assert out.rho[i] < 1e-10
-    for v in (1, 2, 3):
+    for v in (1, 2, 3, 8, 9, 10, 11):
         runs = []
         for graph in (False, True, True):
             for x in xs:
