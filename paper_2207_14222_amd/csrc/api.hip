@@ -396,7 +396,14 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
   while (true) {
     // r = y - A (x + d) in FP64; x <- x + d; r32 = complex64(r)
     if ((rc = finalize_hist(op))) return rc;
-    if ((rc = residual_passes<double2>(op, x, y, B, d, op->r32))) return rc;
+    if (!d && !x_is_guess) {
+      // x = 0: the residual is y itself (relative residual 1) and needs no passes
+      hipLaunchKernelGGL(k_to_c64, dim3(1024), dim3(256), 0, op->st, y, op->r32, op->d.N);
+      LAUNCHCHK("k_to_c64");
+      HIPCHK(hipMemcpyAsync(op->scal, op->scal + 1, sizeof(double), hipMemcpyDeviceToDevice, op->st));
+    } else if ((rc = residual_passes<double2>(op, x, y, B, d, op->r32))) {
+      return rc;
+    }
     HIPCHK(hipMemcpyAsync(host, op->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, op->st));
     if ((rc = pull_hist(op, pulled, it, mon, buf))) return rc;
     pulled = it;
@@ -407,6 +414,7 @@ int solve_refined(usp_op op, const double2* y, double2* x, int x_is_guess, doubl
       if (!(rho < 1.0)) {
         mon.check(it, rho);
         HIPCHK(hipMemsetAsync(x, 0, sizeof(double2) * op->d.N, op->st));
+        x_is_guess = 0;
         continue;
       }
     }
