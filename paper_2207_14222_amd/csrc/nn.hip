@@ -62,6 +62,32 @@ WgradSplit wgrad_split(int D, int H, int cin, int cout, int taps) {
   return {(int)rpc, (int)nch, tg};
 }
 
+// The row-major weight gradient (k_wgrad_rows) serves 3x3x3 shapes whose tap
+// groups come in whole x-rows of taps (TG >= 3) on grids with W % 8 == 0 and
+// V % 32 == 0: chunks of 32-voxel steps, about 4096 waves, partials within
+// 128 MiB.
+struct RowsSplit {
+  bool use;
+  int steps_per_chunk, nchunks;
+};
+RowsSplit rows_split(int D, int H, int W, int cin, int cout, int taps) {
+  const int tg = wgrad_tg(cin, cout, taps);
+  const long V = (long)D * H * W;
+  if (taps != 27 || tg < 3 || W % 8 || V % 32) return {false, 0, 0};
+  const int ng = 27 / tg;
+  const long nsteps = V / 32;
+  long nch = std::min<long>(nsteps, std::max<long>(1, (4096 + ng - 1) / ng));
+  long spc = (nsteps + nch - 1) / nch;
+  nch = (nsteps + spc - 1) / spc;
+  while (nch > 1 && nch * 27L * cout * cin * 4 > (128l << 20)) {
+    spc *= 2;
+    nch = (nsteps + spc - 1) / spc;
+  }
+  return {true, (int)spc, (int)nch};
+}
+// bytes of the channel-major rows of in and g
+long rows_bytes(long V, int cin, int cout) { return (long)align_up(2 * (V + 16) * (long)(cin + cout)); }
+
 constexpr long kBiasChunk = 4096;
 
 bool planes_ok(int c) { return c > 0 && c % 16 == 0; }
@@ -160,8 +186,11 @@ int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, siz
     return fail(USP_ERR_INVALID, "invalid argument");
   const long V = (long)D * H * W;
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
+  const RowsSplit rs = rows_split(D, H, W, cin, cout, taps);
+  const long nch = rs.use ? rs.nchunks : sp.nchunks;
   const long bch = (V + kBiasChunk - 1) / kBiasChunk;
-  *bytes = sizeof(float) * ((long)sp.nchunks * taps * (long)cout * cin + bch * (long)cout) + 256;
+  *bytes = sizeof(float) * (nch * taps * (long)cout * cin + bch * (long)cout) + 256 +
+           (rs.use ? rows_bytes(V, cin, cout) + 256 : 0);
   return 0;
 }
 
@@ -173,21 +202,38 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
   if (ws_bytes < need) return fail(USP_ERR_WORKSPACE, "wgrad workspace too small");
   const long V = (long)D * H * W;
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
+  const RowsSplit rs = rows_split(D, H, W, cin, cout, taps);
+  const int nch = rs.use ? rs.nchunks : sp.nchunks;
   hipStream_t st = (hipStream_t)stream;
-  float* part = (float*)ws;
+  // workspace: [channel-major rows of in and g (row path)] partials, bias partials
+  uint16_t* xr = (uint16_t*)ws;
+  uint16_t* gr = xr + (V + 16) * (long)cin;
+  float* part = (float*)((char*)ws + (rs.use ? rows_bytes(V, cin, cout) : 0));
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
     constexpr int tg = wgrad_tg(ci, co, tp);
+    if constexpr (tp == 27 && tg >= 3) {
+      if (rs.use) {
+        hipLaunchKernelGGL(k_to_rows, dim3(grid_for(V * (ci / 16))), dim3(256), 0, st, (const uint16_t*)in, xr, V,
+                           ci);
+        hipLaunchKernelGGL(k_to_rows, dim3(grid_for(V * (co / 16))), dim3(256), 0, st, (const uint16_t*)g, gr, V,
+                           co);
+        const long items = (long)rs.nchunks * (27 / tg);
+        hipLaunchKernelGGL((k_wgrad_rows<ci, co, tg>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, xr, gr,
+                           part, rs.steps_per_chunk, rs.nchunks, D, H, W);
+        return;
+      }
+    }
     const long items = (long)sp.nchunks * (tp / tg);
     hipLaunchKernelGGL((k_wgrad<ci, co, tp, tg>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st,
                        (const uint16_t*)in, (const uint16_t*)g, part, sp.rows_per_chunk, sp.nchunks, D, H, W);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
   const long n = (long)taps * cout * cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, dw, sp.nchunks, taps,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, dw, nch, taps,
                      cout, cin);
   if (db) {
-    float* bpart = part + (long)sp.nchunks * taps * cout * cin;
+    float* bpart = part + (long)nch * taps * cout * cin;
     const int bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
     hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
                        (int)kBiasChunk);

@@ -444,6 +444,125 @@ k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g, float* 
   }
 }
 
+// Weight gradient from channel-major rows (3x3x3 taps).  The activation and
+// the output gradient are first copied to rows [C][V + 16] (k_to_rows: the
+// V voxels of a channel from index 8, zero guard values on both sides), so
+// the 8 consecutive voxels one lane contributes to a 32-deep product are 16
+// contiguous bytes.  A wave work item = (chunk of 32-voxel steps, group of
+// TG taps); per step, lane group g takes voxels v0 .. v0 + 7 (v0 = 8 (4 s + g),
+// one grid row since W % 8 == 0) and
+//   part[c][tap][co][ci] += sum_v g[co][v] in[ci][v + off(tap)]
+// on v_mfma_f32_16x16x32 bf16: A = 8 voxels of gradient row co, B = 8 shifted
+// voxels of activation row ci (A and B take the same voxel for the same K
+// slot, so the sum is right whatever the order of the slots).  A shift by one
+// voxel along x is assembled from two aligned 16-byte loads with byte-align
+// operations; voxels shifted out of the grid contribute zero.
+__global__ void __launch_bounds__(256) k_to_rows(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, long V,
+                                                 int C) {
+  const long n = (long)(C / 16) * V, pitch = V + 16;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int p = (int)(i / V);
+    const long v = i - (long)p * V;
+    const uint4 q0 = *reinterpret_cast<const uint4*>(in + i * 16);
+    const uint4 q1 = *reinterpret_cast<const uint4*>(in + i * 16 + 8);
+    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      uint16_t* row = out + (long)(16 * p + c) * pitch;
+      row[8 + v] = (uint16_t)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu));
+      if (v < 8) row[v] = 0;            // leading guard
+      if (v < 8) row[8 + V + v] = 0;    // trailing guard
+    }
+  }
+}
+
+// 8 bf16 of a row starting one voxel before (DX = -1), at (0) or after (+1)
+// the aligned position p (p % 8 == 0 in elements); edge_lo / edge_hi zero the
+// value shifted in across the start / end of the grid row.
+template <int DX>
+__device__ __forceinline__ uint4 row8(const uint16_t* __restrict__ row, long p, bool edge_lo, bool edge_hi) {
+  const uint4 cur = *reinterpret_cast<const uint4*>(row + p);
+  if (DX == 0) return cur;
+  if (DX < 0) {
+    uint32_t prev = edge_lo ? 0u : *reinterpret_cast<const uint32_t*>(row + p - 2);
+    uint4 r;
+    r.x = __builtin_amdgcn_alignbit(cur.x, prev, 16);
+    r.y = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
+    r.z = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
+    r.w = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
+    return r;
+  }
+  const uint32_t next = edge_hi ? 0u : *reinterpret_cast<const uint32_t*>(row + p + 8);
+  uint4 r;
+  r.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
+  r.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
+  r.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
+  r.w = __builtin_amdgcn_alignbit(next, cur.w, 16);
+  return r;
+}
+
+template <int CIN, int COUT, int TG>
+__global__ void __launch_bounds__(256)
+k_wgrad_rows(const uint16_t* __restrict__ xr, const uint16_t* __restrict__ gr, float* __restrict__ part,
+             int steps_per_chunk, int nchunks, int D, int H, int W) {
+  constexpr int MT = COUT / 16, NT = CIN / 16, NG = 27 / TG;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const long V = (long)D * H * W, pitch = V + 16, HW = (long)H * W;
+  const int item = blockIdx.x * 4 + wave;
+  if (item >= nchunks * NG) return;  // whole wave; no block barrier in this kernel
+  const int grp = item % NG, c = item / NG;
+  const long nsteps = V / 32;
+  const long s0 = (long)c * steps_per_chunk, s1 = min(s0 + steps_per_chunk, nsteps);
+  v4f acc[TG][MT][NT];
+#pragma unroll
+  for (int t = 0; t < TG; ++t)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[t][mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (long s = s0; s < s1; ++s) {
+    const long v0 = 8 * (4 * s + g);
+    const int z = (int)(v0 / HW), y = (int)((v0 / W) % H), x0 = (int)(v0 % W);
+    v8bf a[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      a[mt] = as_v8bf(*reinterpret_cast<const uint4*>(gr + (long)(mt * 16 + i) * pitch + 8 + v0));
+#pragma unroll
+    for (int t = 0; t < TG; ++t) {
+      const int tap = grp * TG + t;
+      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+      const int zz = z + dz, yy = y + dy;
+      const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
+      const long p = 8 + v0 + (long)dz * HW + (long)dy * W;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        uint4 q = make_uint4(0u, 0u, 0u, 0u);
+        if (ok) {
+          const uint16_t* row = xr + (long)(nt * 16 + i) * pitch;
+          q = dx < 0 ? row8<-1>(row, p, x0 == 0, false)
+                     : (dx > 0 ? row8<1>(row, p, false, x0 + 8 == W) : row8<0>(row, p, false, false));
+        }
+        const v8bf b = as_v8bf(q);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[t][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[t][mt][nt], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds D[co = mt*16 + 4 g + e][ci = nt*16 + i]
+#pragma unroll
+  for (int t = 0; t < TG; ++t) {
+    float* dst = part + ((long)c * 27 + grp * TG + t) * (long)COUT * CIN;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * g + e) * CIN + nt * 16 + i] = acc[t][mt][nt][e];
+  }
+}
+
 // dw[co][tap][ci] = sum over chunks c (in increasing order within each of 16
 // interleaved lanes, then the 16 lane sums in order) of part[c][tap][co][ci].
 __global__ void __launch_bounds__(1024)
