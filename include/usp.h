@@ -582,8 +582,12 @@ int usp_nn_conv3d(const void* in_dev, const void* wpacked_dev, const float* bias
 
 /* Weight (and bias) gradient of usp_nn_conv3d (sign +1):
  *   dw[co][tap][ci] = sum_v in[v + off(tap)][ci] g[v][co],  db[co] = sum_v g[v][co]
- * (fp32, deterministic: per-chunk partials in ws, added in chunk order).
- * db may be NULL.  ws: usp_nn_wgrad_workspace bytes. */
+ * (fp32, deterministic: per-chunk partials in ws, added in a fixed order).
+ * db may be NULL.  ws: usp_nn_wgrad_workspace bytes.  Schedule: 3x3x3
+ * convolutions on grids with W % 32 == 0 copy in and g to voxel-blocked rows
+ * in ws (in zero-padded in y and z) and sweep chunks of rows along y with all
+ * 27 taps per wave (db from the same sweep); other shapes sum per row chunk
+ * and tap group from the planes. */
 int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, size_t* bytes);
 int usp_nn_conv3d_wgrad(const void* in_dev, const void* g_dev, float* dw_dev, float* db_dev, void* ws_dev,
                         size_t ws_bytes, int D, int H, int W, int cin, int cout, int taps, void* stream);

@@ -62,31 +62,44 @@ WgradSplit wgrad_split(int D, int H, int cin, int cout, int taps) {
   return {(int)rpc, (int)nch, tg};
 }
 
-// The row-major weight gradient (k_wgrad_rows) serves 3x3x3 shapes whose tap
-// groups come in whole x-rows of taps (TG >= 3) on grids with W % 8 == 0 and
-// V % 32 == 0: chunks of 32-voxel steps, about 4096 waves, partials within
-// 128 MiB.
-struct RowsSplit {
+// The y-sweep weight gradient (k_wgrad_roll) serves 3x3x3 convolutions on
+// grids with W % 32 == 0: chunks = (plane, 32 voxels of x, a run of ny rows),
+// one wave per chunk and 16 x 16 channel tile.  The rows are split into the
+// fewest runs that give at least 1536 waves (six per CU; the kernel holds two
+// per SIMD), with partials within 128 MiB.
+struct RollSplit {
   bool use;
-  int steps_per_chunk, nchunks;
+  int ny, nchunks;
 };
-RowsSplit rows_split(int D, int H, int W, int cin, int cout, int taps) {
-  const int tg = wgrad_tg(cin, cout, taps);
-  const long V = (long)D * H * W;
-  if (taps != 27 || tg < 3 || W % 8 || V % 32) return {false, 0, 0};
-  const int ng = 27 / tg;
-  const long nsteps = V / 32;
-  long nch = std::min<long>(nsteps, std::max<long>(1, (4096 + ng - 1) / ng));
-  long spc = (nsteps + nch - 1) / nch;
-  nch = (nsteps + spc - 1) / spc;
-  while (nch > 1 && nch * 27L * cout * cin * 4 > (128l << 20)) {
-    spc *= 2;
-    nch = (nsteps + spc - 1) / spc;
-  }
-  return {true, (int)spc, (int)nch};
+RollSplit roll_split(int D, int H, int W, int cin, int cout, int taps) {
+  if (taps != 27 || W % 32) return {false, 0, 0};
+  const long tiles = (long)(cin / 16) * (cout / 16);
+  const long base = (long)D * (W / 32);
+  auto part_bytes = [&](long nyp) { return nyp * base * 27L * cout * cin * 4; };
+  long nyp = 1;
+  while (nyp * base * tiles < 1536 && nyp * 2 <= H && part_bytes(nyp * 2) <= (128l << 20)) nyp *= 2;
+  const long ny = (H + nyp - 1) / nyp;
+  nyp = (H + ny - 1) / ny;
+  if (nyp * base * tiles >= (1l << 31)) return {false, 0, 0};
+  return {true, (int)ny, (int)(nyp * base)};
 }
-// bytes of the channel-major rows of in and g
-long rows_bytes(long V, int cin, int cout) { return (long)align_up(2 * (V + 16) * (long)(cin + cout)); }
+// bytes of the zero-padded activation copy and of the gradient copy
+long xpad_bytes(int D, int H, int W, int cin) { return (long)align_up(2L * (D + 2) * (H + 2) * W * cin); }
+long gblk_bytes(long V, int cout) { return (long)align_up(2 * V * (long)cout); }
+
+// Segments of the two-pass partial reduction: about 2048 blocks of 256 outputs
+// in pass 1, at most kMaxSeg segments.
+constexpr int kMaxSeg = 64;
+struct SegPlan {
+  int seg, nseg;
+};
+SegPlan seg_plan(int nchunks, long n) {
+  const long cols = (n + 255) / 256;
+  long nseg = std::min<long>(std::min<long>(kMaxSeg, nchunks), std::max<long>(1, (2048 + cols - 1) / cols));
+  const long seg = (nchunks + nseg - 1) / nseg;
+  nseg = (nchunks + seg - 1) / seg;
+  return {(int)seg, (int)nseg};
+}
 
 constexpr long kBiasChunk = 4096;
 
@@ -185,12 +198,17 @@ int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, siz
   if (!bytes || D < 1 || H < 1 || W < 1 || !planes_ok(cin) || !planes_ok(cout) || (taps != 1 && taps != 27))
     return fail(USP_ERR_INVALID, "invalid argument");
   const long V = (long)D * H * W;
+  const RollSplit rs = roll_split(D, H, W, cin, cout, taps);
+  if (rs.use) {
+    *bytes = xpad_bytes(D, H, W, cin) + gblk_bytes(V, cout) +
+             sizeof(float) * ((long)rs.nchunks * taps * cout * cin + (long)rs.nchunks * cout +
+                              (long)kMaxSeg * taps * cout * cin) + 256;
+    return 0;
+  }
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
-  const RowsSplit rs = rows_split(D, H, W, cin, cout, taps);
-  const long nch = rs.use ? rs.nchunks : sp.nchunks;
   const long bch = (V + kBiasChunk - 1) / kBiasChunk;
-  *bytes = sizeof(float) * (nch * taps * (long)cout * cin + bch * (long)cout) + 256 +
-           (rs.use ? rows_bytes(V, cin, cout) + 256 : 0);
+  *bytes = sizeof(float) * ((long)sp.nchunks * taps * cout * cin + bch * (long)cout + (long)kMaxSeg * taps * cout * cin) +
+           256;
   return 0;
 }
 
@@ -201,42 +219,54 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
   if (usp_nn_wgrad_workspace(D, H, W, cin, cout, taps, &need)) return USP_ERR_INVALID;
   if (ws_bytes < need) return fail(USP_ERR_WORKSPACE, "wgrad workspace too small");
   const long V = (long)D * H * W;
+  const RollSplit rs = roll_split(D, H, W, cin, cout, taps);
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
-  const RowsSplit rs = rows_split(D, H, W, cin, cout, taps);
   const int nch = rs.use ? rs.nchunks : sp.nchunks;
   hipStream_t st = (hipStream_t)stream;
-  // workspace: [channel-major rows of in and g (row path)] partials, bias partials
-  uint16_t* xr = (uint16_t*)ws;
-  uint16_t* gr = xr + (V + 16) * (long)cin;
-  float* part = (float*)((char*)ws + (rs.use ? rows_bytes(V, cin, cout) : 0));
+  // workspace: [padded activation copy, gradient copy (y sweep)] partials, bias partials
+  uint16_t* xp = (uint16_t*)ws;
+  uint16_t* gb = (uint16_t*)((char*)ws + (rs.use ? xpad_bytes(D, H, W, cin) : 0));
+  float* part = (float*)((char*)ws + (rs.use ? xpad_bytes(D, H, W, cin) + gblk_bytes(V, cout) : 0));
+  float* bpart = part + (long)nch * taps * cout * cin;
+  const long bch_max = rs.use ? nch : (V + kBiasChunk - 1) / kBiasChunk;
+  float* seg_sum = bpart + bch_max * cout;
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
-    constexpr int tg = wgrad_tg(ci, co, tp);
-    if constexpr (tp == 27 && tg >= 3) {
+    if constexpr (tp == 27) {
       if (rs.use) {
-        hipLaunchKernelGGL(k_to_rows, dim3(grid_for(V * (ci / 16))), dim3(256), 0, st, (const uint16_t*)in, xr, V,
-                           ci);
-        hipLaunchKernelGGL(k_to_rows, dim3(grid_for(V * (co / 16))), dim3(256), 0, st, (const uint16_t*)g, gr, V,
-                           co);
-        const long items = (long)rs.nchunks * (27 / tg);
-        hipLaunchKernelGGL((k_wgrad_rows<ci, co, tg>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st, xr, gr,
-                           part, rs.steps_per_chunk, rs.nchunks, D, H, W);
+        const long tiles = (V / 8 + 15) / 16;
+        hipLaunchKernelGGL(k_to_blocks_padded, dim3((unsigned)std::min<long>(tiles * (ci / 16), 1l << 20)), dim3(256),
+                           0, st, (const uint16_t*)in, xp, D, H, W, ci);
+        const long nz = (2L * (D + 2) + 2L * H) * W * ci / 8;
+        hipLaunchKernelGGL(k_zero_padding_rows, dim3(grid_for(nz)), dim3(256), 0, st, xp, D, H, W, ci);
+        hipLaunchKernelGGL(k_to_blocks, dim3((unsigned)std::min<long>(tiles * (co / 16), 1l << 20)), dim3(256), 0,
+                           st, (const uint16_t*)g, gb, V, co);
+        const long items = (long)rs.nchunks * (ci / 16) * (co / 16);
+        const int nlog = (int)((items + 3) / 4);
+        hipLaunchKernelGGL((k_wgrad_roll<ci, co>), dim3((unsigned)((nlog + 7) / 8 * 8)), dim3(256), 0, st, xp, gb,
+                           part, db ? bpart : nullptr, rs.ny, rs.nchunks, D, H, W, nlog);
         return;
       }
     }
+    constexpr int tg = wgrad_tg(ci, co, tp);
     const long items = (long)sp.nchunks * (tp / tg);
     hipLaunchKernelGGL((k_wgrad<ci, co, tp, tg>), dim3((unsigned)((items + 3) / 4)), dim3(256), 0, st,
                        (const uint16_t*)in, (const uint16_t*)g, part, sp.rows_per_chunk, sp.nchunks, D, H, W);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
   const long n = (long)taps * cout * cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 63) / 64)), dim3(1024), 0, st, part, dw, nch, taps,
-                     cout, cin);
+  const SegPlan sg = seg_plan(nch, n);
+  hipLaunchKernelGGL(k_wgrad_reduce_seg, dim3((unsigned)((n + 255) / 256), sg.nseg), dim3(256), 0, st, part, seg_sum,
+                     nch, sg.seg, n);
+  hipLaunchKernelGGL(k_wgrad_reduce_fin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seg_sum, dw, sg.nseg,
+                     taps, cout, cin);
   if (db) {
-    float* bpart = part + (long)nch * taps * cout * cin;
-    const int bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
-    hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
-                       (int)kBiasChunk);
+    int bch = nch;
+    if (!rs.use) {
+      bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
+      hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
+                         (int)kBiasChunk);
+    }
     hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, st, bpart, db, bch, cout);
   }
   LAUNCHCHK("k_wgrad");

@@ -444,144 +444,280 @@ k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g, float* 
   }
 }
 
-// Weight gradient from channel-major rows (3x3x3 taps).  The activation and
-// the output gradient are first copied to rows [C][V + 16] (k_to_rows: the
-// V voxels of a channel from index 8, zero guard values on both sides), so
-// the 8 consecutive voxels one lane contributes to a 32-deep product are 16
-// contiguous bytes.  A wave work item = (chunk of 32-voxel steps, group of
-// TG taps); per step, lane group g takes voxels v0 .. v0 + 7 (v0 = 8 (4 s + g),
-// one grid row since W % 8 == 0) and
-//   part[c][tap][co][ci] += sum_v g[co][v] in[ci][v + off(tap)]
-// on v_mfma_f32_16x16x32 bf16: A = 8 voxels of gradient row co, B = 8 shifted
-// voxels of activation row ci (A and B take the same voxel for the same K
-// slot, so the sum is right whatever the order of the slots).  A shift by one
-// voxel along x is assembled from two aligned 16-byte loads with byte-align
-// operations; voxels shifted out of the grid contribute zero.
-__global__ void __launch_bounds__(256) k_to_rows(const uint16_t* __restrict__ in, uint16_t* __restrict__ out, long V,
-                                                 int C) {
-  const long n = (long)(C / 16) * V, pitch = V + 16;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int p = (int)(i / V);
-    const long v = i - (long)p * V;
-    const uint4 q0 = *reinterpret_cast<const uint4*>(in + i * 16);
-    const uint4 q1 = *reinterpret_cast<const uint4*>(in + i * 16 + 8);
-    const uint32_t w[8] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w};
+// Weight gradient of a 3x3x3 convolution as a sweep along y (grids with
+// W % 32 == 0).  The activation and the output gradient are first copied from
+// the 16-channel planes to voxel-blocked rows: element (c, v) at
+// (block(v) C + c) 8 + v % 8, so the 8 consecutive voxels of one channel that a
+// lane contributes to a 32-deep product are 16 contiguous bytes and the 16
+// channels of an operand 256 contiguous bytes.  The activation copy carries a
+// zero plane before and after the grid in z and a zero row before and after
+// every plane in y ([(D + 2)][(H + 2)][W / 8][C][8]), so every load of it is in
+// bounds and needs no mask; the gradient copy is unpadded ([V / 8][C][8]).
+//
+// A wave owns one chunk (plane z, 32 voxels of x, a run of rows y) and one
+// 16 x 16 tile (gradient channels co, activation channels ci) and accumulates
+// all 27 taps,
+//   part[chunk][tap][co][ci] = sum_v g[co][v] in[ci][v + off(tap)],
+// on v_mfma_f32_16x16x32 bf16 with K = 32 voxels (lane group j of the wave
+// takes voxels x0 + 8 j .. + 7; A and B take the same voxel for the same K
+// slot, so the sum is right whatever the order of the slots).  The x offset of
+// a tap is moved onto the gradient: sum_v g[v] in[v + dx] = sum_u g[u - dx]
+// in[u] with g = 0 outside the grid row, so B is always an aligned 16-byte load
+// of activation row (z + dz, y + dy) and only the three A operands g[u + 1],
+// g[u], g[u - 1] are assembled per step, from one aligned load and the two
+// neighbouring dwords, with byte-align operations.  The nine activation rows
+// of a step are held in registers as a window over (dz, dy); each step loads
+// the three rows y + 2 of planes z - 1, z, z + 1 and the gradient row y + 1 for
+// the next step, and four register slots rotate through the unrolled loop.
+// With bpart the waves of the first activation tile also sum the gradient
+// (one more product against a B of ones): bpart[chunk][co] = sum_v g[co][v].
+// Consecutive chunks run along z and the logical blocks are dealt to XCDs in
+// contiguous ranges, so the three planes a row is read for share an L2.
+__global__ void __launch_bounds__(256) k_to_blocks(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                                                   long V, int C) {
+  // block: plane p, 128 voxels (16 blocks of 8); LDS rows of 20 u16 per voxel
+  __shared__ __align__(16) uint16_t sh[128 * 20];
+  const long nb = V / 8;
+  const long tiles = (nb + 15) / 16;
+  const int np = C / 16;
+  for (long t = blockIdx.x; t < tiles * np; t += gridDim.x) {
+    const int p = (int)(t % np);
+    const long b0 = (t / np) * 16;
+    const int tv = threadIdx.x >> 1, half = threadIdx.x & 1;
+    const long v = b0 * 8 + tv;
+    if (v < V) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in + ((long)p * V + v) * 16 + 8 * half);
+      uint2* d = reinterpret_cast<uint2*>(sh + tv * 20 + 8 * half);
+      d[0] = make_uint2(q.x, q.y);
+      d[1] = make_uint2(q.z, q.w);
+    }
+    __syncthreads();
+    const int bl = threadIdx.x >> 4, c = threadIdx.x & 15;
+    if (b0 + bl < nb) {
+      uint32_t w[4];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      uint16_t* row = out + (long)(16 * p + c) * pitch;
-      row[8 + v] = (uint16_t)((c & 1) ? (w[c >> 1] >> 16) : (w[c >> 1] & 0xffffu));
-      if (v < 8) row[v] = 0;            // leading guard
-      if (v < 8) row[8 + V + v] = 0;    // trailing guard
+      for (int k = 0; k < 4; ++k)
+        w[k] = (uint32_t)sh[(8 * bl + 2 * k) * 20 + c] | ((uint32_t)sh[(8 * bl + 2 * k + 1) * 20 + c] << 16);
+      *reinterpret_cast<uint4*>(out + (((b0 + bl) * C) + 16 * p + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+  }
+}
+
+// planes -> zero-padded voxel-blocked rows [(D + 2)][(H + 2)][W / 8][C][8] (interior only)
+__global__ void __launch_bounds__(256) k_to_blocks_padded(const uint16_t* __restrict__ in,
+                                                          uint16_t* __restrict__ out, int D, int H, int W, int C) {
+  __shared__ __align__(16) uint16_t sh[128 * 20];
+  const long V = (long)D * H * W, nb = V / 8;
+  const long tiles = (nb + 15) / 16;
+  const int np = C / 16, wb = W / 8;
+  for (long t = blockIdx.x; t < tiles * np; t += gridDim.x) {
+    const int p = (int)(t % np);
+    const long b0 = (t / np) * 16;
+    const int tv = threadIdx.x >> 1, half = threadIdx.x & 1;
+    const long v = b0 * 8 + tv;
+    if (v < V) {
+      const uint4 q = *reinterpret_cast<const uint4*>(in + ((long)p * V + v) * 16 + 8 * half);
+      uint2* d = reinterpret_cast<uint2*>(sh + tv * 20 + 8 * half);
+      d[0] = make_uint2(q.x, q.y);
+      d[1] = make_uint2(q.z, q.w);
+    }
+    __syncthreads();
+    const int bl = threadIdx.x >> 4, c = threadIdx.x & 15;
+    const long b = b0 + bl;
+    if (b < nb) {
+      uint32_t w[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[k] = (uint32_t)sh[(8 * bl + 2 * k) * 20 + c] | ((uint32_t)sh[(8 * bl + 2 * k + 1) * 20 + c] << 16);
+      const long zy = b / wb, xb = b - zy * wb;
+      const long z = zy / H, y = zy - z * H;
+      const long pb = ((z + 1) * (H + 2) + (y + 1)) * wb + xb;
+      *reinterpret_cast<uint4*>(out + ((pb * C) + 16 * p + c) * 8) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    __syncthreads();
+  }
+}
+
+// the zero rows of the padded layout: rows 0 and H + 1 of the D + 2 planes, rows 1 .. H of planes 0 and D + 1
+__global__ void __launch_bounds__(256) k_zero_padding_rows(uint16_t* __restrict__ out, int D, int H, int W, int C) {
+  const long row = (long)W * C / 8;  // 16-byte units per padded row
+  const long n = (2L * (D + 2) + 2L * H) * row;
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+    const long r = k / row, e = k - r * row;
+    long z, y;
+    if (r < 2L * (D + 2)) {
+      z = r >> 1;
+      y = (r & 1) ? H + 1 : 0;
+    } else {
+      const long q = r - 2L * (D + 2);
+      y = (q >> 1) + 1;
+      z = (q & 1) ? D + 1 : 0;
+    }
+    reinterpret_cast<uint4*>(out + (z * (H + 2) + y) * (long)W * C)[e] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
+// one step of the y sweep: products of gradient row y with activation rows
+// y - 1, y, y + 1 (sm, s0, sp; three planes each) for the 27 taps, and the
+// loads of the next step (sn: row y + 2 through xnext, the padded row y + 3
+// clamped to the last padded row; gn/pn/nn: gradient row y + 1 through gnext)
+template <bool BIAS>
+__device__ __forceinline__ void wgrad_roll_step(v4f (&acc)[27], v4f& accb, const uint4 (&sm)[3], const uint4 (&s0)[3],
+                                                const uint4 (&sp)[3], uint4 (&sn)[3], const uint4& gc, uint32_t gpv,
+                                                uint32_t gnx, uint4& gn, uint32_t& pn, uint32_t& nn,
+                                                const uint16_t* __restrict__ xnext, long PZ,
+                                                const uint16_t* __restrict__ gnext, int dprev, int dnext,
+                                                uint32_t mprev, uint32_t mnext) {
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) sn[dz] = *reinterpret_cast<const uint4*>(xnext + dz * PZ);
+  gn = *reinterpret_cast<const uint4*>(gnext);
+  pn = *reinterpret_cast<const uint32_t*>(gnext + dprev) & mprev;
+  nn = *reinterpret_cast<const uint32_t*>(gnext + dnext) & mnext;
+  // gm = g[u + 1] (tap dx = -1), gc = g[u] (dx = 0), gp = g[u - 1] (dx = +1)
+  uint4 gm, gp;
+  gm.x = __builtin_amdgcn_alignbit(gc.y, gc.x, 16);
+  gm.y = __builtin_amdgcn_alignbit(gc.z, gc.y, 16);
+  gm.z = __builtin_amdgcn_alignbit(gc.w, gc.z, 16);
+  gm.w = __builtin_amdgcn_alignbit(gnx, gc.w, 16);
+  gp.x = __builtin_amdgcn_alignbit(gc.x, gpv, 16);
+  gp.y = __builtin_amdgcn_alignbit(gc.y, gc.x, 16);
+  gp.z = __builtin_amdgcn_alignbit(gc.z, gc.y, 16);
+  gp.w = __builtin_amdgcn_alignbit(gc.w, gc.z, 16);
+  const v8bf a0 = as_v8bf(gm), a1 = as_v8bf(gc), a2 = as_v8bf(gp);
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const v8bf b = as_v8bf(dy == 0 ? sm[dz] : (dy == 1 ? s0[dz] : sp[dz]));
+      const int t = dz * 9 + dy * 3;
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b, acc[t], 0, 0, 0);
+      acc[t + 1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, acc[t + 1], 0, 0, 0);
+      acc[t + 2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b, acc[t + 2], 0, 0, 0);
+    }
+  if (BIAS) {
+    const uint4 ones = make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u);  // bf16 1.0 x 8
+    accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, as_v8bf(ones), accb, 0, 0, 0);
+  }
+}
+
+template <int CIN, int COUT, bool BIAS>
+__device__ __forceinline__ void wgrad_roll_body(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb,
+                                                float* __restrict__ part, float* __restrict__ bpart, int chunk,
+                                                int nt, int mt, int ny, int D, int H, int W) {
+  const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
+  const int nxs = W / 32;
+  const int z = chunk % D, xs = (chunk / D) % nxs, yp = chunk / (D * nxs);
+  const int y0 = yp * ny, y1 = min(y0 + ny, H);
+  const int x0 = xs * 32 + 8 * j;
+  const int xoff = x0 * CIN + (nt * 16 + i) * 8;   // lane's element offset within an activation row
+  const int goff = x0 * COUT + (mt * 16 + i) * 8;  // and within a gradient row
+  const int dprev = x0 == 0 ? 0 : -COUT * 8 + 6, dnext = x0 + 8 == W ? 0 : COUT * 8;
+  const uint32_t mprev = x0 == 0 ? 0u : ~0u, mnext = x0 + 8 == W ? 0u : ~0u;
+  const long PY = (long)W * CIN, PZ = (long)(H + 2) * PY, GY = (long)W * COUT;
+  v4f acc[27], accb = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  // padded plane z is grid plane z - 1; padded row y is grid row y - 1
+  const uint16_t* xz = xp + (long)z * PZ + xoff;
+  uint4 S0[3], S1[3], S2[3], S3[3];
+  {
+    const long r0 = (long)min(y0, H + 1) * PY, r1 = (long)min(y0 + 1, H + 1) * PY, r2 = (long)min(y0 + 2, H + 1) * PY;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz) {
+      S0[dz] = *reinterpret_cast<const uint4*>(xz + dz * PZ + r0);
+      S1[dz] = *reinterpret_cast<const uint4*>(xz + dz * PZ + r1);
+      S2[dz] = *reinterpret_cast<const uint4*>(xz + dz * PZ + r2);
     }
   }
-}
-
-// 8 bf16 of a row starting one voxel before (DX = -1), at (0) or after (+1)
-// the aligned position p (p % 8 == 0 in elements); edge_lo / edge_hi zero the
-// value shifted in across the start / end of the grid row.
-template <int DX>
-__device__ __forceinline__ uint4 row8(const uint16_t* __restrict__ row, long p, bool edge_lo, bool edge_hi) {
-  const uint4 cur = *reinterpret_cast<const uint4*>(row + p);
-  if (DX == 0) return cur;
-  if (DX < 0) {
-    uint32_t prev = edge_lo ? 0u : *reinterpret_cast<const uint32_t*>(row + p - 2);
-    uint4 r;
-    r.x = __builtin_amdgcn_alignbit(cur.x, prev, 16);
-    r.y = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
-    r.z = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
-    r.w = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
-    return r;
+  const uint16_t* gz = gb + (long)z * H * GY + goff;
+  const uint16_t* g0 = gz + (long)min(y0, H - 1) * GY;
+  uint4 G0 = *reinterpret_cast<const uint4*>(g0), G1;
+  uint32_t P0 = *reinterpret_cast<const uint32_t*>(g0 + dprev) & mprev, P1;
+  uint32_t N0 = *reinterpret_cast<const uint32_t*>(g0 + dnext) & mnext, N1;
+#define USP_WG_STEP(SM, S0_, SP, SN, GC, PC, NC, GN, PN, NN, YY)                                                   \
+  wgrad_roll_step<BIAS>(acc, accb, SM, S0_, SP, SN, GC, PC, NC, GN, PN, NN, xz + (long)min((YY) + 3, H + 1) * PY, PZ, \
+                        gz + (long)min((YY) + 1, H - 1) * GY, dprev, dnext, mprev, mnext)
+  for (int y = y0; y < y1; y += 4) {
+    USP_WG_STEP(S0, S1, S2, S3, G0, P0, N0, G1, P1, N1, y);
+    if (y + 1 < y1) USP_WG_STEP(S1, S2, S3, S0, G1, P1, N1, G0, P0, N0, y + 1);
+    if (y + 2 < y1) USP_WG_STEP(S2, S3, S0, S1, G0, P0, N0, G1, P1, N1, y + 2);
+    if (y + 3 < y1) USP_WG_STEP(S3, S0, S1, S2, G1, P1, N1, G0, P0, N0, y + 3);
   }
-  const uint32_t next = edge_hi ? 0u : *reinterpret_cast<const uint32_t*>(row + p + 8);
-  uint4 r;
-  r.x = __builtin_amdgcn_alignbit(cur.y, cur.x, 16);
-  r.y = __builtin_amdgcn_alignbit(cur.z, cur.y, 16);
-  r.z = __builtin_amdgcn_alignbit(cur.w, cur.z, 16);
-  r.w = __builtin_amdgcn_alignbit(next, cur.w, 16);
-  return r;
+#undef USP_WG_STEP
+  // lane holds D[co = mt*16 + 4 j + e][ci = nt*16 + i]
+#pragma unroll
+  for (int t = 0; t < 27; ++t) {
+    float* dst = part + ((long)chunk * 27 + t) * (long)COUT * CIN;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * j + e) * CIN + nt * 16 + i] = acc[t][e];
+  }
+  if (BIAS && i == 0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) bpart[(long)chunk * COUT + mt * 16 + 4 * j + e] = accb[e];
+  }
 }
 
-template <int CIN, int COUT, int TG>
+// work item = (chunk, co tile mt, ci tile nt), nt fastest; chunk = (y part, x segment, z), z fastest.
+// Logical block L = 4 items; the launch has a multiple of 8 blocks and block b runs logical block
+// (b % 8) (grid / 8) + b / 8, so each XCD takes a contiguous range of chunks.
+template <int CIN, int COUT>
 __global__ void __launch_bounds__(256)
-k_wgrad_rows(const uint16_t* __restrict__ xr, const uint16_t* __restrict__ gr, float* __restrict__ part,
-             int steps_per_chunk, int nchunks, int D, int H, int W) {
-  constexpr int MT = COUT / 16, NT = CIN / 16, NG = 27 / TG;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int i = lane & 15, g = lane >> 4;
-  const long V = (long)D * H * W, pitch = V + 16, HW = (long)H * W;
-  const int item = blockIdx.x * 4 + wave;
-  if (item >= nchunks * NG) return;  // whole wave; no block barrier in this kernel
-  const int grp = item % NG, c = item / NG;
-  const long nsteps = V / 32;
-  const long s0 = (long)c * steps_per_chunk, s1 = min(s0 + steps_per_chunk, nsteps);
-  v4f acc[TG][MT][NT];
-#pragma unroll
-  for (int t = 0; t < TG; ++t)
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) acc[t][mt][nt] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (long s = s0; s < s1; ++s) {
-    const long v0 = 8 * (4 * s + g);
-    const int z = (int)(v0 / HW), y = (int)((v0 / W) % H), x0 = (int)(v0 % W);
-    v8bf a[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-      a[mt] = as_v8bf(*reinterpret_cast<const uint4*>(gr + (long)(mt * 16 + i) * pitch + 8 + v0));
-#pragma unroll
-    for (int t = 0; t < TG; ++t) {
-      const int tap = grp * TG + t;
-      const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-      const int zz = z + dz, yy = y + dy;
-      const bool ok = zz >= 0 && zz < D && yy >= 0 && yy < H;
-      const long p = 8 + v0 + (long)dz * HW + (long)dy * W;
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        uint4 q = make_uint4(0u, 0u, 0u, 0u);
-        if (ok) {
-          const uint16_t* row = xr + (long)(nt * 16 + i) * pitch;
-          q = dx < 0 ? row8<-1>(row, p, x0 == 0, false)
-                     : (dx > 0 ? row8<1>(row, p, false, x0 + 8 == W) : row8<0>(row, p, false, false));
-        }
-        const v8bf b = as_v8bf(q);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-          acc[t][mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[t][mt][nt], 0, 0, 0);
-      }
-    }
-  }
-  // lane holds D[co = mt*16 + 4 g + e][ci = nt*16 + i]
-#pragma unroll
-  for (int t = 0; t < TG; ++t) {
-    float* dst = part + ((long)c * 27 + grp * TG + t) * (long)COUT * CIN;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * g + e) * CIN + nt * 16 + i] = acc[t][mt][nt][e];
-  }
+k_wgrad_roll(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb, float* __restrict__ part,
+             float* __restrict__ bpart, int ny, int nchunks, int D, int H, int W, int nlog) {
+  constexpr int NT = CIN / 16, MT = COUT / 16, NS = NT * MT;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int per = gridDim.x / 8;
+  const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (L >= nlog) return;
+  const int item = L * 4 + wave;
+  if (item >= nchunks * NS) return;  // whole wave; no block barrier in this kernel
+  const int chunk = item / NS, sub = item % NS, nt = sub % NT, mt = sub / NT;
+  if (bpart && nt == 0)
+    wgrad_roll_body<CIN, COUT, true>(xp, gb, part, bpart, chunk, nt, mt, ny, D, H, W);
+  else
+    wgrad_roll_body<CIN, COUT, false>(xp, gb, part, bpart, chunk, nt, mt, ny, D, H, W);
 }
 
-// dw[co][tap][ci] = sum over chunks c (in increasing order within each of 16
-// interleaved lanes, then the 16 lane sums in order) of part[c][tap][co][ci].
-__global__ void __launch_bounds__(1024)
-k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dw, int nchunks, int taps, int cout, int cin) {
-  __shared__ float sh[16][65];
-  const long n = (long)taps * cout * cin;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const long j = (long)blockIdx.x * 64 + tx;
+// dw[co][tap][ci] = sum over chunks c of part[c][tap][co][ci], in two passes
+// with a fixed order: pass 1 sums the chunks of segment s (seg consecutive
+// chunks, in increasing order) into seg_sum[s][j]; pass 2 adds the segments in
+// increasing order and writes dw.  j = (tap cout + co) cin + ci.
+__global__ void __launch_bounds__(256)
+k_wgrad_reduce_seg(const float* __restrict__ part, float* __restrict__ seg_sum, int nchunks, int seg, long n) {
+  const long j = (long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const int c0 = blockIdx.y * seg, c1 = min(c0 + seg, nchunks);
+  // loads issued eight at a time, added in chunk order
   float s = 0.f;
-  if (j < n)
-    for (int c = ty; c < nchunks; c += 16) s += part[(long)c * n + j];
-  sh[ty][tx] = s;
-  __syncthreads();
-  if (ty == 0 && j < n) {
-    float t = 0.f;
-    for (int q = 0; q < 16; ++q) t += sh[q][tx];
-    const int tap = (int)(j / ((long)cout * cin)), co = (int)((j / cin) % cout), ci = (int)(j % cin);
-    dw[((long)co * taps + tap) * cin + ci] = t;
+  int c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = part[(long)(c + k) * n + j];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += v[k];
   }
+  for (; c < c1; ++c) s += part[(long)c * n + j];
+  seg_sum[(long)blockIdx.y * n + j] = s;
+}
+__global__ void __launch_bounds__(256)
+k_wgrad_reduce_fin(const float* __restrict__ seg_sum, float* __restrict__ dw, int nseg, int taps, int cout, int cin) {
+  const long n = (long)taps * cout * cin;
+  const long j = (long)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float t = 0.f;
+  int q = 0;
+  for (; q + 8 <= nseg; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = seg_sum[(long)(q + k) * n + j];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t += v[k];
+  }
+  for (; q < nseg; ++q) t += seg_sum[(long)q * n + j];
+  const int tap = (int)(j / ((long)cout * cin)), co = (int)((j / cin) % cout), ci = (int)(j % cin);
+  dw[((long)co * taps + tap) * cin + ci] = t;
 }
 
 __device__ __forceinline__ void unpack8(uint4 q, float* f) {

@@ -78,10 +78,12 @@ def pack(L, w, transposed):
 
 
 SHAPES = [(16, 16, 27), (16, 32, 27), (64, 128, 27), (192, 64, 27), (48, 16, 27), (16, 16, 1)]
-GRIDS = [(8, 16, 16), (16, 32, 32), (64, 64, 64), (256, 32, 32)]   # the last two take the LDS-staged schedules
+# global-load schedules; (32, 7, 32) splits the weight gradient's y sweep into uneven runs (7 = 4 + 3, 2 + 2 + 2 + 1)
+GRIDS = [(8, 16, 16), (16, 32, 32), (32, 7, 32)]
+WIDE_GRIDS = [(64, 64, 64), (256, 32, 32)]   # the LDS-staged schedules
 
 
-@pytest.mark.parametrize("grid", GRIDS[:2])
+@pytest.mark.parametrize("grid", GRIDS)
 @pytest.mark.parametrize("cin,cout,taps", SHAPES)
 def test_conv_forward_input_grad_and_weight_grad(cin, cout, taps, grid):
     _need_gpu()
@@ -137,13 +139,13 @@ def conv_at(xc, w, b, z, y, x, sign):
     return out
 
 
-@pytest.mark.parametrize("grid", GRIDS[2:])
+@pytest.mark.parametrize("grid", WIDE_GRIDS)
 @pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (16, 48), (96, 32)])
 def test_conv_wide_schedule(cin, cout, grid):
     """Grids of 2^18 voxels (the LDS-staged schedules, 64-wide and 16-wide bricks):
     forward and input gradient against direct float64 sums on sampled voxels
-    (faces, corners and brick edges included); the 16 -> 16 weight gradient in
-    full (row chunks of a larger grid)."""
+    (faces, corners and brick edges included); the weight gradient in full
+    (the voxel-blocked copies and step chunks of a larger grid)."""
     _need_gpu()
     L = _lib()
     D, H, W = grid
@@ -176,20 +178,19 @@ def test_conv_wide_schedule(cin, cout, grid):
         assert np.linalg.norm(outn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
         r = conv_at(gyn, wn.transpose(2, 1, 0), None, z, y, x_, -1)
         assert np.linalg.norm(gxn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
-    if cin == cout == 16:
-        nb = ct.c_size_t()
-        assert L.lib().usp_nn_wgrad_workspace(D, H, W, cin, cout, 27, ct.byref(nb)) == 0
-        ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
-        dw = torch.empty(cout, 27, cin, dtype=torch.float32, device="cuda")
-        assert L.lib().usp_nn_conv3d_wgrad(_p(x), _p(gy), _p(dw), None, _p(ws), nb.value, D, H, W, cin, cout, 27,
-                                           _st()) == 0
-        xp = np.pad(xn, ((0, 0), (1, 1), (1, 1), (1, 1)))
-        G = gyn.reshape(cout, -1)
-        ref = np.empty((cout, 27, cin))
-        for tap in range(27):
-            kz, ky, kx = tap // 9, (tap // 3) % 3, tap % 3
-            ref[:, tap, :] = G @ xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(cin, -1).T
-        assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
+    nb = ct.c_size_t()
+    assert L.lib().usp_nn_wgrad_workspace(D, H, W, cin, cout, 27, ct.byref(nb)) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.empty(cout, 27, cin, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d_wgrad(_p(x), _p(gy), _p(dw), None, _p(ws), nb.value, D, H, W, cin, cout, 27,
+                                       _st()) == 0
+    xp = np.pad(xn, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    G = gyn.reshape(cout, -1)
+    ref = np.empty((cout, 27, cin))
+    for tap in range(27):
+        kz, ky, kx = tap // 9, (tap // 3) % 3, tap % 3
+        ref[:, tap, :] = G @ xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(cin, -1).T
+    assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
 def test_pool_upsample_and_copies():
