@@ -193,6 +193,40 @@ def test_conv_wide_schedule(cin, cout, grid):
     assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
+@pytest.mark.parametrize("grid", [(1, 1, 32), (2, 3, 96), (5, 2, 64), (3, 9, 32)])
+@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (192, 64)])
+def test_weight_gradient_sweep_edge_grids(cin, cout, grid):
+    """The y-sweep weight gradient (and its bias) on grids that exercise its edges:
+    a single plane and row (every neighbour in the zero padding), a width of three
+    32-voxel segments, and few rows split into runs of one and two (the runs that
+    stop inside a four-step group are in the first test's (32, 7, 32) grid);
+    against float64 sums over the zero-padded grid."""
+    _need_gpu()
+    L = _lib()
+    D, H, W = grid
+    print(f"[gpu-case] wgrad sweep {cin}->{cout} grid {grid}", flush=True)
+    g = torch.Generator().manual_seed(11 + cin + cout + D + H + W)
+    xc = bf(torch.randn(cin, D, H, W, generator=g))
+    gyc = bf(torch.randn(cout, D, H, W, generator=g))
+    x, gy = from_cf(xc).cuda(), from_cf(gyc).cuda()
+    nb = ct.c_size_t()
+    assert L.lib().usp_nn_wgrad_workspace(D, H, W, cin, cout, 27, ct.byref(nb)) == 0
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    dw = torch.empty(cout, 27, cin, dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d_wgrad(_p(x), _p(gy), _p(dw), _p(db), _p(ws), nb.value, D, H, W, cin, cout, 27,
+                                       _st()) == 0
+    xn, gyn = xc.double().numpy(), gyc.double().numpy()
+    xp = np.pad(xn, ((0, 0), (1, 1), (1, 1), (1, 1)))
+    G = gyn.reshape(cout, -1)
+    ref = np.empty((cout, 27, cin))
+    for tap in range(27):
+        kz, ky, kx = tap // 9, (tap // 3) % 3, tap % 3
+        ref[:, tap, :] = G @ xp[:, kz:kz + D, ky:ky + H, kx:kx + W].reshape(cin, -1).T
+    assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
+    assert rel(db.cpu().double(), gyc.double().sum(dim=(1, 2, 3))) < 1e-4
+
+
 def test_pool_upsample_and_copies():
     _need_gpu()
     L = _lib()
