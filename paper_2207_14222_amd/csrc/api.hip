@@ -554,8 +554,8 @@ int krylov_layout(usp_op op, int method, int restart, KWork* kw) {
   const long mb = (N + 256L * kMdotKE - 1) / (256L * kMdotKE);
   kw->N = N;
   kw->pitch = std::max<long>(std::max<long>(xb, mb), kVecBlocks);
-  kw->nvec = method == USP_KRYLOV_BICGSTAB ? 6 : method == USP_KRYLOV_CG ? 3 : restart + 3;
-  kw->nrows = method == USP_KRYLOV_GMRES ? std::max(5, 2 * (restart + 1)) : 5;
+  kw->nvec = method == USP_KRYLOV_BICGSTAB ? 6 : method == USP_KRYLOV_CG ? 4 : restart + 3;
+  kw->nrows = method == USP_KRYLOV_GMRES ? std::max(5, 2 * (restart + 1)) : 6;
   kw->vec_bytes = align_up(N * es);
   kw->total = kw->vec_bytes * kw->nvec + align_up(sizeof(double) * kw->nrows * kw->pitch) + sizeof(double) * kKsDoubles;
   return 0;
@@ -703,14 +703,16 @@ int solve_bicgstab(usp_op op, const C* y, C* x, int x_is_guess, double tol, int 
 }
 
 // Conjugate gradients on P x = b for a Hermitian canonical operator (A, L, V
-// Hermitian; P is then Hermitian, and positive definite when A is).  An
-// iteration is four launches: k_cg_first (beta from the summed |r|^2
-// partials, p = r + beta p, B p and its FFT along n2), the strided passes,
-// k_klast (q = P p with the <p, q> partials) and k_cg_update (alpha from the
-// summed partials, x and r, |r|^2 partials).  Every block sums the partial
-// rows it needs in the same fixed order, so no scalar kernel or host round
-// trip sits between them; |r|^2 alternates between two rows (2 and 3).  The
-// host synchronises at true-residual checks only.
+// Hermitian; P is then Hermitian, and positive definite when A is), in the
+// Chronopoulos-Gear arrangement: the two inner products of an iteration
+// (|r|^2 and r^H P r) come from the same pass and s = P p is carried by a
+// recurrence, so the vector update joins the first pass of the next operator
+// application.  An iteration is three launches: k_cgcg_first (alpha, beta
+// from the summed partials, p, s, x, r and the FFT along n2 of B r), the
+// strided passes, and k_klast (w = P r with the <w, r> and |r|^2 partials).
+// Every block sums the partial rows it needs in the same fixed order, so no
+// scalar kernel or host round trip sits between them.  The host synchronises
+// at true-residual checks only.
 // first_check > 0: the first check at that iteration, then every check_every
 // (a caller that knows roughly how many iterations a solve takes checks
 // around the end only); 0: every check_every from the start.
@@ -721,52 +723,45 @@ int solve_cg(usp_op op, const C* y, C* x, int x_is_guess, double tol, int maxit,
   const long n = op->d.N;
   const Dims& D = op->d;
   const int nlines = D.n0 * D.n1;
-  C *r = kw.vec<C>(0), *p = kw.vec<C>(1), *q = kw.vec<C>(2);
+  C *r = kw.vec<C>(0), *p = kw.vec<C>(1), *s = kw.vec<C>(2), *w = kw.vec<C>(3);
   double* ks = kw.ks;
-  // grid of the vector kernels: every block of the next pass sums their
-  // partial row, so small problems use fewer (fuller) blocks
-  const int vb = std::min(vec_blocks(n), (int)std::max<long>(256, n / 4096));
-  const int xb = x_blocks<C>(op);
-  double* rrow[2] = {kw.rows + 2 * kw.pitch, kw.rows + 3 * kw.pitch};
+  const int vb = vec_blocks(n);
+  const int xb = x_blocks<C>(op);   // blocks of the last pass = width of its partial rows
   int rc;
   if ((rc = norm2(op, y, op->scal + 1))) return rc;
   HIPCHK(hipMemsetAsync(ks, 0, sizeof(double) * 32, op->st));
   if ((rc = kapply<C>(op, y, r, true, nullptr, 0, kw))) return rc;   // r = b
   if (x_is_guess) {
-    if ((rc = kapply<C>(op, x, q, false, nullptr, 0, kw))) return rc;
-    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, (const C*)q, n, rrow[0]);
-    LAUNCHCHK("k_ksub");                                              // p = b - P x, |r_0|^2 partials
+    if ((rc = kapply<C>(op, x, w, false, nullptr, 0, kw))) return rc;
+    hipLaunchKernelGGL(k_ksub<C>, dim3(vb), dim3(256), 0, op->st, p, (const C*)r, (const C*)w, n, kw.rows);
+    LAUNCHCHK("k_ksub");                                              // p = b - P x
     HIPCHK(hipMemcpyAsync(r, p, sizeof(C) * n, hipMemcpyDeviceToDevice, op->st));
   } else {
     HIPCHK(hipMemsetAsync(x, 0, sizeof(C) * n, op->st));
-    hipLaunchKernelGGL(k_knorm2<C>, dim3(vb), dim3(256), 0, op->st, (const C*)r, n, rrow[0]);
-    LAUNCHCHK("k_knorm2");
   }
   HIPCHK(hipMemsetAsync(p, 0, sizeof(C) * n, op->st));
+  HIPCHK(hipMemsetAsync(s, 0, sizeof(C) * n, op->st));
+  // w_0 = P r_0 with <w, r> (rows 2, 3) and |r|^2 (row 5)
+  if ((rc = kapply<C>(op, r, w, false, nullptr, 2 | 8, kw))) return rc;
   int it = 0, status = USP_MAXIT;
   while (it < maxit) {
-    const int cur = it & 1;
     bool ok = with_n(D.n2, [&](auto NC) {
       constexpr int N = decltype(NC)::value;
       constexpr int TPB = x_threads<C>();
       constexpr int LPB = TPB / (N / PassPlan<N>::E);
       const int blocks = (nlines + LPB - 1) / LPB;
-      hipLaunchKernelGGL((k_cg_first<C, N>), dim3(blocks), dim3(TPB), 0, op->st, (C*)op->t, p, (const C*)r,
-                         (const C*)op->B, tw_for<C>(op, N), nlines, (const double*)rrow[cur],
-                         it > 0 ? (const double*)rrow[cur ^ 1] : (const double*)nullptr, vb);
+      hipLaunchKernelGGL((k_cgcg_first<C, N>), dim3(blocks), dim3(TPB), 0, op->st, (C*)op->t, x, r, p, s,
+                         (const C*)w, (const C*)op->B, tw_for<C>(op, N), nlines, (const double*)kw.rows, kw.pitch, xb,
+                         ks, it);
     });
     if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "contiguous axis length");
-    LAUNCHCHK("k_cg_first");
-    if ((rc = kapply_tail<C>(op, p, q, false, p, 1, kw))) return rc;   // q = P p, <p, q> in rows 0, 1
-    hipLaunchKernelGGL(k_cg_update<C>, dim3(vb), dim3(256), 0, op->st, x, r, (const C*)p, (const C*)q, n,
-                       (const double*)rrow[cur], vb, (const double*)kw.rows, (const double*)(kw.rows + kw.pitch), xb,
-                       rrow[cur ^ 1], ks);
-    LAUNCHCHK("cg iteration");
+    LAUNCHCHK("k_cgcg_first");                                       // x_{it+1}, r_{it+1}, t = F B r
+    if ((rc = kapply_tail<C>(op, r, w, false, nullptr, 2 | 8, kw))) return rc;   // w = P r, <w, r>, |r|^2
     ++it;
     if ((it >= first_check && (it - first_check) % check_every == 0) || it == maxit) {
       double rho, hk[2];
       if ((rc = krylov_check<C>(op, y, x, &rho))) return rc;
-      if ((rc = ksum(op, kw, 2 + (it & 1), 1, vb, ks + KS_CRR))) return rc;   // |r_it|^2
+      if ((rc = ksum(op, kw, 5, 1, xb, ks + KS_CRR))) return rc;   // |r_it|^2
       HIPCHK(hipMemcpyAsync(hk, ks + KS_FLAG, sizeof(double), hipMemcpyDeviceToHost, op->st));
       HIPCHK(hipMemcpyAsync(hk + 1, ks + KS_CRR, sizeof(double), hipMemcpyDeviceToHost, op->st));
       HIPCHK(hipStreamSynchronize(op->st));

@@ -21,6 +21,8 @@ enum KSlot {
   KS_RHO = 0, KS_RHON = 2, KS_ALPHA = 4, KS_OMEGA = 6, KS_BETA = 8, KS_RV = 10, KS_TS = 12, KS_TT = 14,
   KS_RR = 15, KS_FLAG = 16, KS_NRM = 17,
   KS_CRR = 18,   // CG: |r|^2 at a check
+  KS_CGG = 20,   // CG: gamma_i = |r_i|^2 in slot 20 + (i & 1)
+  KS_CGA = 22,   // CG: alpha_i (complex) in slots 22 + 2 (i & 1), + 1
   KS_H = 32, KS_COEF = 512
 };
 enum KScalMode { KSM_INIT = 0, KSM_BETA = 1, KSM_ALPHA = 2, KSM_OMEGA = 3 };
@@ -132,7 +134,7 @@ k_kfirst(C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ B, co
 // Last pass: u = inverse FFT along n2 of t (already scaled by 1/(N (l + 1))),
 // w = B (v - u) (RHS = false) or w = B u (RHS = true; v unused).  Dot partials,
 // one row each (row pitch `pitch`): bit 0 <q, w> (rows 0, 1), bit 1 <w, v>
-// (rows 2, 3), bit 2 |w|^2 (row 4).
+// (rows 2, 3), bit 2 |w|^2 (row 4), bit 3 |v|^2 (row 5; RHS = false).
 template <class C, int N, bool RHS>
 __global__ void __launch_bounds__(x_threads<C>())
 k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ B, C* __restrict__ w,
@@ -147,7 +149,7 @@ k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ 
   __shared__ double scratch[64];
   load_twiddles<C, N>(tws, tw);
   const int tid = threadIdx.x;
-  double qr = 0.0, qi = 0.0, wr = 0.0, wi = 0.0, ww = 0.0;
+  double qr = 0.0, qi = 0.0, wr = 0.0, wi = 0.0, ww = 0.0, vv2 = 0.0;
   if (tid < TH) {
     const int tt = tid % T, li = tid / T;
     const long line = (long)blockIdx.x * LPB + li;
@@ -175,6 +177,7 @@ k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ 
         if (dots & 1) cdot_acc(q[p], out, qr, qi);
         if (dots & 2) cdot_acc(out, vv, wr, wi);
         if (dots & 4) ww += (double)out.x * out.x + (double)out.y * out.y;
+        if (dots & 8) vv2 += (double)vv.x * vv.x + (double)vv.y * vv.y;
       }
     }
   } else {
@@ -183,6 +186,7 @@ k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ 
   if (dots & 1) block_partial2(qr, qi, scratch, rows, rows + pitch);
   if (dots & 2) block_partial2(wr, wi, scratch, rows + 2 * pitch, rows + 3 * pitch);
   if (dots & 4) block_partial(ww, scratch, rows + 4 * pitch);
+  if (dots & 8) block_partial(vv2, scratch, rows + 5 * pitch);
 }
 
 // ---- vector kernels (grid-stride; per-block partial rows of width gridDim.x) ----
@@ -251,14 +255,21 @@ __device__ __forceinline__ double row_total(const double* __restrict__ row, int 
   return block_sum(acc, scratch);
 }
 
-// Fused CG step, first pass of P p: beta = |r_i|^2 / |r_{i-1}|^2 from the two
-// alternating |r|^2 partial rows (rr_cur, rr_prev; beta = 0 when rr_prev is
-// NULL), p = r + beta p, then t = FFT along n2 of B p.
+// CG step in the Chronopoulos-Gear arrangement (one reduction point per
+// iteration; s = P p is carried by a recurrence instead of recomputed):
+//   gamma_i = |r_i|^2 (row 5) and delta_i = r_i^H w_i (rows 2, 3 hold
+//   <w, r> = conj(delta)) with w_i = P r_i, both summed from the last pass's
+//   partials; beta_i = gamma_i / gamma_{i-1}, alpha_i = gamma_i / (delta_i -
+//   beta_i gamma_i / alpha_{i-1}) (beta_0 = 0, alpha_0 = gamma_0 / delta_0);
+//   p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+// then t = FFT along n2 of B r for the next P r.  Every block derives the same
+// scalars; block 0 keeps gamma_i and alpha_i in the ks slots of parity i for
+// step i + 1.  A zero denominator gives alpha = 0 and raises ks[KS_FLAG].
 template <class C, int N>
 __global__ void __launch_bounds__(x_threads<C>())
-k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const C* __restrict__ B,
-           const C* __restrict__ tw, int nlines, const double* __restrict__ rr_cur, const double* __restrict__ rr_prev,
-           int nrr) {
+k_cgcg_first(C* __restrict__ t, C* __restrict__ x, C* __restrict__ r, C* __restrict__ p, C* __restrict__ s,
+             const C* __restrict__ w, const C* __restrict__ B, const C* __restrict__ tw, int nlines,
+             const double* __restrict__ rows, long pitch, int nrow, double* __restrict__ ks, int it) {
   using PP = PassPlan<N>;
   using Rr = typename real_of<C>::type;
   constexpr int E = PP::E, T = N / E;
@@ -267,10 +278,30 @@ k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const 
   __shared__ C lds[LPB * LdsRow<C>::padded(N)];
   __shared__ C tws[N];
   __shared__ double scratch[64];
-  double beta = 0.0;
-  if (rr_prev) {
-    const double a = row_total(rr_cur, nrr, scratch), b = row_total(rr_prev, nrr, scratch);
-    beta = b > 0.0 ? a / b : 0.0;
+  const double g = row_total(rows + 5 * pitch, nrow, scratch);
+  const double dr = row_total(rows + 2 * pitch, nrow, scratch), di = -row_total(rows + 3 * pitch, nrow, scratch);
+  double beta = 0.0, ar = 0.0, ai = 0.0;
+  bool bad = false;
+  if (it == 0) {
+    if (dr == 0.0 && di == 0.0) bad = true;
+    else zdiv(g, 0.0, dr, di, ar, ai);
+  } else {
+    const int q = (it - 1) & 1;
+    const double gp = ks[KS_CGG + q], apr = ks[KS_CGA + 2 * q], api = ks[KS_CGA + 2 * q + 1];
+    beta = gp > 0.0 ? g / gp : 0.0;
+    double cr = 0.0, ci = 0.0;
+    if (apr == 0.0 && api == 0.0) bad = true;
+    else zdiv(beta * g, 0.0, apr, api, cr, ci);
+    const double er = dr - cr, ei = di - ci;
+    if (bad || (er == 0.0 && ei == 0.0)) bad = true;
+    else zdiv(g, 0.0, er, ei, ar, ai);
+  }
+  if (bad || !(ar == ar && ai == ai)) ar = ai = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ks[KS_CGG + (it & 1)] = g;
+    ks[KS_CGA + 2 * (it & 1)] = ar;
+    ks[KS_CGA + 2 * (it & 1) + 1] = ai;
+    if (bad) ks[KS_FLAG] += 1.0;
   }
   load_twiddles<C, N>(tws, tw);
   const int tid = threadIdx.x;
@@ -278,6 +309,7 @@ k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const 
     idle_fft_syncs<N, typename PP::P>();
     return;
   }
+  const C alpha = mk<C>(ar, ai);
   const int tt = tid % T, li = tid / T;
   const long line = (long)blockIdx.x * LPB + li;
   const bool active = line < nlines;
@@ -290,8 +322,13 @@ k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const 
     C val = mk<C>(0.0, 0.0);
     if (active) {
       const C pn = cadd(r[q], cscale(p[q], (Rr)beta));
+      const C sn = cadd(w[q], cscale(s[q], (Rr)beta));
       p[q] = pn;
-      val = cmul(B[q], pn);
+      s[q] = sn;
+      x[q] = cadd(x[q], cmul(alpha, pn));
+      const C rn = csub(r[q], cmul(alpha, sn));
+      r[q] = rn;
+      val = cmul(B[q], rn);
     }
     a[e] = val;
   }
@@ -302,35 +339,6 @@ k_cg_first(C* __restrict__ t, C* __restrict__ p, const C* __restrict__ r, const 
   }
 }
 
-// Fused CG step, update: alpha = |r_i|^2 / <p, P p> from the partial rows
-// (rr_cur: nrr partials; pq_re, pq_im: npq partials each), x += alpha p,
-// r -= alpha q, and the partials of |r_{i+1}|^2 into rr_next.  A zero <p, P p>
-// (breakdown) gives alpha = 0 and raises ks[KS_FLAG].
-template <class C>
-__global__ void __launch_bounds__(256) k_cg_update(C* __restrict__ x, C* __restrict__ r, const C* __restrict__ p,
-                                                   const C* __restrict__ q, long n, const double* __restrict__ rr_cur,
-                                                   int nrr, const double* __restrict__ pq_re,
-                                                   const double* __restrict__ pq_im, int npq,
-                                                   double* __restrict__ rr_next, double* __restrict__ ks) {
-  __shared__ double scratch[64];
-  const double rr = row_total(rr_cur, nrr, scratch);
-  const double dr = row_total(pq_re, npq, scratch), di = row_total(pq_im, npq, scratch);
-  double ar = 0.0, ai = 0.0;
-  if (dr == 0.0 && di == 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) ks[KS_FLAG] += 1.0;
-  } else {
-    zdiv(rr, 0.0, dr, di, ar, ai);
-  }
-  const C alpha = mk<C>(ar, ai);
-  double acc = 0.0;
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    x[i] = cadd(x[i], cmul(alpha, p[i]));
-    const C ri = csub(r[i], cmul(alpha, q[i]));
-    r[i] = ri;
-    acc += (double)ri.x * ri.x + (double)ri.y * ri.y;
-  }
-  block_partial(acc, scratch, rr_next);
-}
 
 // |z|^2 partials in row 0 (grid-stride)
 template <class C>
