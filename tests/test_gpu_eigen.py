@@ -52,6 +52,23 @@ def test_cg_iterates_and_solution():
     assert rel(to_np(r.x), xs) < 1e-9
 
 
+def test_cg_iterates_from_initial_guess():
+    """CG from a nonzero x0 (r_0 = b - P x0 before the first w = P r): K iterates
+    against the oracle's CG from the same x0, complex128 1e-10."""
+    _need_gpu()
+    print("[gpu-case] cg iterates from a guess, double ring 32", flush=True)
+    V, h = media.double_ring_well(n=32, box=6.0)
+    cp, op, can, gop = _pair(V, h, 5.0)
+    y = media.random_start(op.shape, seed=6)
+    x0 = 0.3 * media.random_start(op.shape, seed=7)
+    K = 12
+    r = gop.krylov(torch.from_numpy(y).to("cuda"), x=torch.from_numpy(x0.copy()).to("cuda"), method="cg", tol=1e-30,
+                   maxit=K, check_every=K)
+    ro = krylov.cg(op, y, 1e-30, K, x0=x0)
+    assert r.iterations == K
+    assert rel(to_np(r.x), ro.x) < 1e-10
+
+
 def _match_vectors(U, W):
     """max over columns of 1 - |<u_i, w_i>| (unit vectors, phase-free)."""
     return max(1.0 - abs(np.vdot(U[:, i], W[:, i])) for i in range(U.shape[1]))
