@@ -200,9 +200,10 @@ int usp_nn_wgrad_workspace(int D, int H, int W, int cin, int cout, int taps, siz
   const long V = (long)D * H * W;
   const RollSplit rs = roll_split(D, H, W, cin, cout, taps);
   if (rs.use) {
-    *bytes = xpad_bytes(D, H, W, cin) + gblk_bytes(V, cout) +
-             sizeof(float) * ((long)rs.nchunks * taps * cout * cin + (long)rs.nchunks * cout +
-                              (long)kMaxSeg * taps * cout * cin) + 256;
+    // partial rows of 27 cout cin weights + cout bias sums, and the segment sums of the reduction
+    const long pitch = 27L * cout * cin + cout;
+    *bytes = xpad_bytes(D, H, W, cin) + gblk_bytes(V, cout) + sizeof(float) * ((long)rs.nchunks + kMaxSeg) * pitch +
+             256;
     return 0;
   }
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
@@ -223,13 +224,17 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
   const WgradSplit sp = wgrad_split(D, H, cin, cout, taps);
   const int nch = rs.use ? rs.nchunks : sp.nchunks;
   hipStream_t st = (hipStream_t)stream;
-  // workspace: [padded activation copy, gradient copy (y sweep)] partials, bias partials
+  // workspace: y sweep: padded activation copy, gradient copy, partial rows (weights and bias sums),
+  // segment sums; row chunks: weight partials, bias partials, segment sums
+  const long n = (long)taps * cout * cin;
+  const long pitch = rs.use ? n + cout : n;             // floats between partial rows
+  const long ncols = rs.use && db ? n + cout : n;       // columns the reduction adds up
   uint16_t* xp = (uint16_t*)ws;
   uint16_t* gb = (uint16_t*)((char*)ws + (rs.use ? xpad_bytes(D, H, W, cin) : 0));
   float* part = (float*)((char*)ws + (rs.use ? xpad_bytes(D, H, W, cin) + gblk_bytes(V, cout) : 0));
-  float* bpart = part + (long)nch * taps * cout * cin;
-  const long bch_max = rs.use ? nch : (V + kBiasChunk - 1) / kBiasChunk;
-  float* seg_sum = bpart + bch_max * cout;
+  const long bch = (V + kBiasChunk - 1) / kBiasChunk;   // bias chunks of the row-chunk path
+  float* bpart = part + (long)nch * pitch;               // row-chunk path only
+  float* seg_sum = rs.use ? bpart : bpart + bch * cout;
   bool ok = with_conv_shape(cin, cout, taps, [&](auto CI, auto CO, auto TP) {
     constexpr int ci = decltype(CI)::value, co = decltype(CO)::value, tp = decltype(TP)::value;
     if constexpr (tp == 27) {
@@ -237,14 +242,12 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
         const long tiles = (V / 8 + 15) / 16;
         hipLaunchKernelGGL(k_to_blocks_padded, dim3((unsigned)std::min<long>(tiles * (ci / 16), 1l << 20)), dim3(256),
                            0, st, (const uint16_t*)in, xp, D, H, W, ci);
-        const long nz = (2L * (D + 2) + 2L * H) * W * ci / 8;
-        hipLaunchKernelGGL(k_zero_padding_rows, dim3(grid_for(nz)), dim3(256), 0, st, xp, D, H, W, ci);
         hipLaunchKernelGGL(k_to_blocks, dim3((unsigned)std::min<long>(tiles * (co / 16), 1l << 20)), dim3(256), 0,
                            st, (const uint16_t*)g, gb, V, co);
         const long items = (long)rs.nchunks * (ci / 16) * (co / 16);
         const int nlog = (int)((items + 3) / 4);
         hipLaunchKernelGGL((k_wgrad_roll<ci, co>), dim3((unsigned)((nlog + 7) / 8 * 8)), dim3(256), 0, st, xp, gb,
-                           part, db ? bpart : nullptr, rs.ny, rs.nchunks, D, H, W, nlog);
+                           part, db ? 1 : 0, rs.ny, rs.nchunks, D, H, W, nlog);
         return;
       }
     }
@@ -254,20 +257,15 @@ int usp_nn_conv3d_wgrad(const void* in, const void* g, float* dw, float* db, voi
                        (const uint16_t*)in, (const uint16_t*)g, part, sp.rows_per_chunk, sp.nchunks, D, H, W);
   });
   if (!ok) return fail(USP_ERR_UNSUPPORTED_SHAPE, "convolution shape not instantiated");
-  const long n = (long)taps * cout * cin;
-  const SegPlan sg = seg_plan(nch, n);
-  hipLaunchKernelGGL(k_wgrad_reduce_seg, dim3((unsigned)((n + 255) / 256), sg.nseg), dim3(256), 0, st, part, seg_sum,
-                     nch, sg.seg, n);
-  hipLaunchKernelGGL(k_wgrad_reduce_fin, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, seg_sum, dw, sg.nseg,
-                     taps, cout, cin);
-  if (db) {
-    int bch = nch;
-    if (!rs.use) {
-      bch = (int)((V + kBiasChunk - 1) / kBiasChunk);
-      hipLaunchKernelGGL(k_bgrad, dim3(bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
-                         (int)kBiasChunk);
-    }
-    hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, st, bpart, db, bch, cout);
+  const SegPlan sg = seg_plan(nch, ncols);
+  hipLaunchKernelGGL(k_wgrad_reduce_seg, dim3((unsigned)((ncols + 255) / 256), sg.nseg), dim3(256), 0, st, part,
+                     pitch, seg_sum, nch, sg.seg, ncols);
+  hipLaunchKernelGGL(k_wgrad_reduce_fin, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, st, seg_sum, ncols, dw,
+                     db, sg.nseg, taps, cout, cin);
+  if (db && !rs.use) {
+    hipLaunchKernelGGL(k_bgrad, dim3((unsigned)bch, cout / 16), dim3(256), 0, st, (const uint16_t*)g, bpart, V, cout,
+                       (int)kBiasChunk);
+    hipLaunchKernelGGL(k_bgrad_reduce, dim3(cout), dim3(256), 0, st, bpart, db, (int)bch, cout);
   }
   LAUNCHCHK("k_wgrad");
   return 0;

@@ -469,8 +469,9 @@ k_wgrad(const uint16_t* __restrict__ in, const uint16_t* __restrict__ g, float* 
 // of a step are held in registers as a window over (dz, dy); each step loads
 // the three rows y + 2 of planes z - 1, z, z + 1 and the gradient row y + 1 for
 // the next step, and four register slots rotate through the unrolled loop.
-// With bpart the waves of the first activation tile also sum the gradient
-// (one more product against a B of ones): bpart[chunk][co] = sum_v g[co][v].
+// With bias the waves of the first activation tile also sum the gradient (one
+// more product against a B of ones) into the bias columns of the chunk's
+// partial row: part[chunk][27 COUT CIN + co] = sum_v g[co][v].
 // Consecutive chunks run along z and the logical blocks are dealt to XCDs in
 // contiguous ranges, so the three planes a row is read for share an L2.
 __global__ void __launch_bounds__(256) k_to_blocks(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
@@ -504,7 +505,9 @@ __global__ void __launch_bounds__(256) k_to_blocks(const uint16_t* __restrict__ 
   }
 }
 
-// planes -> zero-padded voxel-blocked rows [(D + 2)][(H + 2)][W / 8][C][8] (interior only)
+// planes -> zero-padded voxel-blocked rows [(D + 2)][(H + 2)][W / 8][C][8]: the
+// interior from the planes, then the zero rows (rows 0 and H + 1 of the D + 2
+// planes, rows 1 .. H of planes 0 and D + 1)
 __global__ void __launch_bounds__(256) k_to_blocks_padded(const uint16_t* __restrict__ in,
                                                           uint16_t* __restrict__ out, int D, int H, int W, int C) {
   __shared__ __align__(16) uint16_t sh[128 * 20];
@@ -537,13 +540,9 @@ __global__ void __launch_bounds__(256) k_to_blocks_padded(const uint16_t* __rest
     }
     __syncthreads();
   }
-}
-
-// the zero rows of the padded layout: rows 0 and H + 1 of the D + 2 planes, rows 1 .. H of planes 0 and D + 1
-__global__ void __launch_bounds__(256) k_zero_padding_rows(uint16_t* __restrict__ out, int D, int H, int W, int C) {
   const long row = (long)W * C / 8;  // 16-byte units per padded row
-  const long n = (2L * (D + 2) + 2L * H) * row;
-  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+  const long nz = (2L * (D + 2) + 2L * H) * row;
+  for (long k = blockIdx.x * 256L + threadIdx.x; k < nz; k += (long)gridDim.x * 256) {
     const long r = k / row, e = k - r * row;
     long z, y;
     if (r < 2L * (D + 2)) {
@@ -601,10 +600,13 @@ __device__ __forceinline__ void wgrad_roll_step(v4f (&acc)[27], v4f& accb, const
   }
 }
 
+// partial rows of the weight gradient's sweep: 27 COUT CIN weights, then COUT bias sums
+template <int CIN, int COUT> constexpr long wgrad_row_pitch() { return 27L * COUT * CIN + COUT; }
+
 template <int CIN, int COUT, bool BIAS>
 __device__ __forceinline__ void wgrad_roll_body(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb,
-                                                float* __restrict__ part, float* __restrict__ bpart, int chunk,
-                                                int nt, int mt, int ny, int D, int H, int W) {
+                                                float* __restrict__ part, int chunk, int nt, int mt, int ny, int D,
+                                                int H, int W) {
   const int lane = threadIdx.x & 63, i = lane & 15, j = lane >> 4;
   const int nxs = W / 32;
   const int z = chunk % D, xs = (chunk / D) % nxs, yp = chunk / (D * nxs);
@@ -646,15 +648,16 @@ __device__ __forceinline__ void wgrad_roll_body(const uint16_t* __restrict__ xp,
   }
 #undef USP_WG_STEP
   // lane holds D[co = mt*16 + 4 j + e][ci = nt*16 + i]
+  float* row = part + (long)chunk * wgrad_row_pitch<CIN, COUT>();
 #pragma unroll
   for (int t = 0; t < 27; ++t) {
-    float* dst = part + ((long)chunk * 27 + t) * (long)COUT * CIN;
+    float* dst = row + t * COUT * CIN;
 #pragma unroll
     for (int e = 0; e < 4; ++e) dst[(mt * 16 + 4 * j + e) * CIN + nt * 16 + i] = acc[t][e];
   }
   if (BIAS && i == 0) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) bpart[(long)chunk * COUT + mt * 16 + 4 * j + e] = accb[e];
+    for (int e = 0; e < 4; ++e) row[27 * COUT * CIN + mt * 16 + 4 * j + e] = accb[e];
   }
 }
 
@@ -663,8 +666,8 @@ __device__ __forceinline__ void wgrad_roll_body(const uint16_t* __restrict__ xp,
 // (b % 8) (grid / 8) + b / 8, so each XCD takes a contiguous range of chunks.
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256)
-k_wgrad_roll(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb, float* __restrict__ part,
-             float* __restrict__ bpart, int ny, int nchunks, int D, int H, int W, int nlog) {
+k_wgrad_roll(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb, float* __restrict__ part, int bias,
+             int ny, int nchunks, int D, int H, int W, int nlog) {
   constexpr int NT = CIN / 16, MT = COUT / 16, NS = NT * MT;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int per = gridDim.x / 8;
@@ -673,20 +676,23 @@ k_wgrad_roll(const uint16_t* __restrict__ xp, const uint16_t* __restrict__ gb, f
   const int item = L * 4 + wave;
   if (item >= nchunks * NS) return;  // whole wave; no block barrier in this kernel
   const int chunk = item / NS, sub = item % NS, nt = sub % NT, mt = sub / NT;
-  if (bpart && nt == 0)
-    wgrad_roll_body<CIN, COUT, true>(xp, gb, part, bpart, chunk, nt, mt, ny, D, H, W);
+  if (bias && nt == 0)
+    wgrad_roll_body<CIN, COUT, true>(xp, gb, part, chunk, nt, mt, ny, D, H, W);
   else
-    wgrad_roll_body<CIN, COUT, false>(xp, gb, part, bpart, chunk, nt, mt, ny, D, H, W);
+    wgrad_roll_body<CIN, COUT, false>(xp, gb, part, chunk, nt, mt, ny, D, H, W);
 }
 
-// dw[co][tap][ci] = sum over chunks c of part[c][tap][co][ci], in two passes
-// with a fixed order: pass 1 sums the chunks of segment s (seg consecutive
-// chunks, in increasing order) into seg_sum[s][j]; pass 2 adds the segments in
-// increasing order and writes dw.  j = (tap cout + co) cin + ci.
+// dw[co][tap][ci] = sum over chunks c of part[c][tap][co][ci] (and, for
+// columns past the weights, db[co] = sum over c of part[c][n + co]), in two
+// passes with a fixed order: pass 1 sums the chunks of segment s (seg
+// consecutive chunks, in increasing order) into seg_sum[s][j]; pass 2 adds the
+// segments in increasing order.  Partial rows are `pitch` floats apart, the
+// first ncols of each are reduced; j = (tap cout + co) cin + ci for j < n.
 __global__ void __launch_bounds__(256)
-k_wgrad_reduce_seg(const float* __restrict__ part, float* __restrict__ seg_sum, int nchunks, int seg, long n) {
+k_wgrad_reduce_seg(const float* __restrict__ part, long pitch, float* __restrict__ seg_sum, int nchunks, int seg,
+                   long ncols) {
   const long j = (long)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
+  if (j >= ncols) return;
   const int c0 = blockIdx.y * seg, c1 = min(c0 + seg, nchunks);
   // loads issued eight at a time, added in chunk order
   float s = 0.f;
@@ -694,28 +700,33 @@ k_wgrad_reduce_seg(const float* __restrict__ part, float* __restrict__ seg_sum, 
   for (; c + 8 <= c1; c += 8) {
     float v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = part[(long)(c + k) * n + j];
+    for (int k = 0; k < 8; ++k) v[k] = part[(long)(c + k) * pitch + j];
 #pragma unroll
     for (int k = 0; k < 8; ++k) s += v[k];
   }
-  for (; c < c1; ++c) s += part[(long)c * n + j];
-  seg_sum[(long)blockIdx.y * n + j] = s;
+  for (; c < c1; ++c) s += part[(long)c * pitch + j];
+  seg_sum[(long)blockIdx.y * ncols + j] = s;
 }
 __global__ void __launch_bounds__(256)
-k_wgrad_reduce_fin(const float* __restrict__ seg_sum, float* __restrict__ dw, int nseg, int taps, int cout, int cin) {
+k_wgrad_reduce_fin(const float* __restrict__ seg_sum, long ncols, float* __restrict__ dw, float* __restrict__ db,
+                   int nseg, int taps, int cout, int cin) {
   const long n = (long)taps * cout * cin;
   const long j = (long)blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
+  if (j >= ncols) return;
   float t = 0.f;
   int q = 0;
   for (; q + 8 <= nseg; q += 8) {
     float v[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) v[k] = seg_sum[(long)(q + k) * n + j];
+    for (int k = 0; k < 8; ++k) v[k] = seg_sum[(long)(q + k) * ncols + j];
 #pragma unroll
     for (int k = 0; k < 8; ++k) t += v[k];
   }
-  for (; q < nseg; ++q) t += seg_sum[(long)q * n + j];
+  for (; q < nseg; ++q) t += seg_sum[(long)q * ncols + j];
+  if (j >= n) {
+    db[j - n] = t;
+    return;
+  }
   const int tap = (int)(j / ((long)cout * cin)), co = (int)((j / cin) % cout), ci = (int)(j % cin);
   dw[((long)co * taps + tap) * cin + ci] = t;
 }
