@@ -104,6 +104,7 @@ SegPlan seg_plan(int nchunks, long n) {
 constexpr long kBiasChunk = 4096;
 
 bool planes_ok(int c) { return c > 0 && c % 16 == 0; }
+bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 }  // namespace
 
@@ -313,16 +314,24 @@ int usp_nn_channel_copy(const void* src, int Cs, int s0, void* dst, int Cd, int 
 
 int usp_nn_relu_backward(const void* y, const void* g, void* out, long n, int accumulate, void* stream) {
   if (!y || !g || !out) return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_relu_back, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (const uint16_t*)y,
-                     (const uint16_t*)g, (uint16_t*)out, n, accumulate);
+  if (aligned16(y) && aligned16(g) && aligned16(out) && n % 8 == 0)
+    hipLaunchKernelGGL(k_relu_back8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream, (const uint4*)y,
+                       (const uint4*)g, (uint4*)out, n / 8, accumulate);
+  else
+    hipLaunchKernelGGL(k_relu_back, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (const uint16_t*)y,
+                       (const uint16_t*)g, (uint16_t*)out, n, accumulate);
   LAUNCHCHK("k_relu_back");
   return 0;
 }
 
 int usp_nn_add(void* dst, const void* src, long n, void* stream) {
   if (!dst || !src) return fail(USP_ERR_INVALID, "invalid argument");
-  hipLaunchKernelGGL(k_add_bf, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (uint16_t*)dst,
-                     (const uint16_t*)src, n);
+  if (aligned16(dst) && aligned16(src) && n % 8 == 0)
+    hipLaunchKernelGGL(k_add_bf8, dim3(grid_for(n / 8)), dim3(256), 0, (hipStream_t)stream, (uint4*)dst,
+                       (const uint4*)src, n / 8);
+  else
+    hipLaunchKernelGGL(k_add_bf, dim3(grid_for(n)), dim3(256), 0, (hipStream_t)stream, (uint16_t*)dst,
+                       (const uint16_t*)src, n);
   LAUNCHCHK("k_add_bf");
   return 0;
 }

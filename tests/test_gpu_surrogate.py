@@ -227,6 +227,34 @@ def test_weight_gradient_sweep_edge_grids(cin, cout, grid):
     assert rel(db.cpu().double(), gyc.double().sum(dim=(1, 2, 3))) < 1e-4
 
 
+@pytest.mark.parametrize("n,offset", [(16 * 4096, 0), (16 * 4096 - 8, 8), (1000, 1), (13, 0)])
+def test_relu_backward_and_add_match_definition(n, offset):
+    """ReLU backward (out = g where y > 0, else 0; plus out when accumulating)
+    and the bf16 add, bit for bit against float arithmetic rounded to bf16: the
+    16-byte path (aligned, n % 8 == 0) and the element path (an offset of one
+    element misaligns the operands; ragged n)."""
+    _need_gpu()
+    L = _lib()
+    print(f"[gpu-case] relu backward / add n {n} offset {offset}", flush=True)
+    g = torch.Generator().manual_seed(n + offset)
+    def mk():
+        return torch.randn(n + offset, generator=g).to(torch.bfloat16).cuda()
+    y, gr, out0 = mk(), mk(), mk()
+    yv, gv = y[offset:], gr[offset:]
+    for acc in (0, 1):
+        out = out0.clone()
+        ov = out[offset:]
+        assert L.lib().usp_nn_relu_backward(_p(yv), _p(gv), _p(ov), n, acc, _st()) == 0
+        ref = torch.where(yv.float() > 0, gv.float(), torch.zeros_like(gv.float()))
+        if acc:
+            ref = ref + out0[offset:].float()
+        assert torch.equal(ov.cpu(), ref.to(torch.bfloat16).cpu()), acc
+    dst = out0.clone()
+    dv = dst[offset:]
+    assert L.lib().usp_nn_add(_p(dv), _p(gv), n, _st()) == 0
+    assert torch.equal(dv.cpu(), (out0[offset:].float() + gv.float()).to(torch.bfloat16).cpu())
+
+
 def test_pool_upsample_and_copies():
     _need_gpu()
     L = _lib()
