@@ -627,7 +627,9 @@ int usp_nn_features(const void* nidx_dev, void* out_dev, int D, int H, int W, do
 /* Relative squared L2 loss ||scale p - x||^2 / ||x||^2 between the prediction
  * p (fp32 [V][2], Re/Im) and the target field x (complex64 [V]); grad (may be
  * NULL) receives its gradient with respect to p as bf16 [V][16] (channels
- * >= 2 zero).  ws: 32 KiB.  Synchronises; the loss is written to *loss_out. */
+ * >= 2 zero).  ws: 32 KiB.  With loss_out the call synchronises and writes
+ * the loss there; with loss_out NULL it does not synchronise and leaves the
+ * loss (a double) at byte offset 16384 of ws, valid once the stream reaches it. */
 int usp_nn_loss(const float* pred_dev, const void* target_dev, float scale, long V, void* grad_dev, void* ws_dev,
                 double* loss_out, void* stream);
 

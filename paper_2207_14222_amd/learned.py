@@ -106,17 +106,21 @@ def train(net: UNet3D, wl: Workload, data, epochs=3, lr=2e-3, seed=0, log=None):
     rng = np.random.default_rng(seed)
     steps = max(1, epochs * len(data))
     hist = []
+    # per-step losses stay on the device (no host round trip inside an epoch)
+    hist_dev = torch.empty(len(data), dtype=torch.float64, device=wl.device)
     s = 0
     t0 = time.perf_counter()
     for ep in range(epochs):
-        for j in rng.permutation(len(data)):
+        for k, j in enumerate(rng.permutation(len(data))):
             nre, x = data[j]
             wl.features(net, nre)
             net.forward()
-            hist.append(net.loss(x, grad=True))
+            net.loss(x, grad=True, sync=False)
+            hist_dev[k] = net.loss_device()
             net.backward()
             net.adam_step(lr=float(lr * 0.5 * (1.0 + np.cos(np.pi * s / steps))))
             s += 1
+        hist.extend(hist_dev.cpu().tolist())
         if log:
             log(f"epoch {ep + 1}/{epochs}: mean loss {np.mean(hist[-len(data):]):.4f} "
                 f"({time.perf_counter() - t0:.1f} s)")

@@ -237,13 +237,19 @@ class UNet3D:
         self._conv("head", a.d1, a.pred, relu=False, out_f32=True, cstore=2)
         return a.pred
 
-    def loss(self, target64, grad=True):
-        """Relative squared L2 error of scale * pred against the target field (complex64)."""
+    def loss(self, target64, grad=True, sync=True):
+        """Relative squared L2 error of scale * pred against the target field (complex64).
+        With sync=False nothing waits for the device: the value stays in the loss
+        workspace (``loss_device()``) and None is returned."""
         out = np.zeros(1)
         L.check(L.lib().usp_nn_loss(_p(self.a.pred), _p(target64), self.scale, self.V[0],
                                     _p(self.gout) if grad else None, _p(self.lossws),
-                                    out.ctypes.data_as(ct.POINTER(ct.c_double)), _s(self.dev)))
-        return float(out[0])
+                                    out.ctypes.data_as(ct.POINTER(ct.c_double)) if sync else None, _s(self.dev)))
+        return float(out[0]) if sync else None
+
+    def loss_device(self):
+        """The last loss as a 0-dim float64 device tensor (a view of the loss workspace)."""
+        return self.lossws[16384:16392].view(torch.float64)[0]
 
     def _add(self, dst, src):
         L.check(L.lib().usp_nn_add(_p(dst), _p(src), dst.numel(), _s(self.dev)))
