@@ -121,12 +121,32 @@ template <int DIR> struct Dft<1, DIR> {
 template <class C> struct LdsRow {
   C* base;
   __device__ __forceinline__ C& operator[](int p) const { return base[p + (p >> 4)]; }
+  // position a + k, k a compile-time offset of the unrolled loops:
+  // (a + k) >> 4 = (a >> 4) + (k >> 4) when (a mod 16) + (k mod 16) < 16,
+  // which holds for every access of the pass and line plans below, so the
+  // thread's part is computed once and k stays an immediate offset
+  __device__ __forceinline__ C& at(int a, int k) const { return base[a + (a >> 4) + k + (k >> 4)]; }
   static constexpr int padded(int n) { return n + (n >> 4); }
 };
 // Column of a [pos][W] tile (strided passes): pitch W + 1.
 template <class C, int W> struct LdsCol {
   C* base;
   __device__ __forceinline__ C& operator[](int p) const { return base[p * (W + 1)]; }
+  __device__ __forceinline__ C& at(int a, int k) const { return (*this)[a + k]; }
+};
+// Column of a [pos][W] tile with pitch W and one spare row every 16
+// positions (N (W + W / 16) slots): the stride-16 writes of a radix-16 stage
+// (positions 16 j + q) and the stride-T reads that follow spread over all
+// banks, which the pitch W + 1 does not give them when W <= 8, and the
+// address stays affine in the unrolled index.
+template <class C, int W> struct LdsColP {
+  C* base;
+  __device__ __forceinline__ C& operator[](int p) const { return base[(p + (p >> 4)) * W]; }
+  // (a + k) >> 4 = (a >> 4) + (k >> 4) when (a mod 16) + (k mod 16) < 16,
+  // which holds for every access of the 16 x 16 x 4 plan (stage 1 writes
+  // 16 j + q, stage 2 writes (j mod 16) + 256 (j / 16) + 16 q, reads t + 64 e):
+  // the thread's part is computed once and k stays an immediate offset
+  __device__ __forceinline__ C& at(int a, int k) const { return base[(a + (a >> 4)) * W + (k + (k >> 4)) * W]; }
 };
 
 // One Stockham stage.  `tw` is the forward twiddle table exp(-2 pi i k / N),
@@ -159,13 +179,13 @@ __device__ __forceinline__ void fft_stage(C (&v)[E], int t, const Line& line, co
     } else {
       const int base = (j / Ns) * Ns * R + (j & (Ns - 1));
 #pragma unroll
-      for (int q = 0; q < R; ++q) line[base + q * Ns] = a[q];
+      for (int q = 0; q < R; ++q) line.at(base, q * Ns) = a[q];
     }
   }
   if (!LAST) {
     sync();
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = line[t + T * e];
+    for (int e = 0; e < E; ++e) v[e] = line.at(t, T * e);
     sync();
   }
 }
@@ -212,6 +232,16 @@ template <> struct LinePlan<1024> { using P = Plan<4, 4, 4, 4, 4>; static conste
 
 struct BlockSync {
   __device__ __forceinline__ void operator()() const { __syncthreads(); }
+};
+// Exchange barrier for a line held by a single wave: the LDS performs one
+// wave's accesses in issue order, so only the compiler must keep the writes
+// before the reads (and the reads before the next stage's writes).
+struct WaveSync {
+  __device__ __forceinline__ void operator()() const {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
 };
 
 // Reductions ----------------------------------------------------------------

@@ -97,7 +97,8 @@ template <int N, class P> __device__ __forceinline__ void idle_fft_syncs() {
 
 // Contiguous-axis pass.  Cc: compute (and spectrum storage) type; Cx: storage
 // type of x, y, B.  Body for LPB lines starting at line0 (TH = LPB*T
-// threads take part; threads >= TH only join the barriers and must form whole
+// threads take part; threads >= TH only join the block barriers (none when a
+// line fits in one wave) and must form whole
 // waves).  tws: twiddles in LDS; lds: LPB padded rows.  Returns the thread's
 // partial sum of |Delta|^2 (X_FUSED, in the precision of Cc) or |r|^2 (X_RINV).
 // FL (fused pass only): bit 0 = load x, B, y before the inverse FFT;
@@ -115,8 +116,13 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
   constexpr int E = PP::E, T = N / E;
   constexpr int TH = LPB * T;
   constexpr int PADN = LdsRow<Cc>::padded(N);
+  // lines of at most 64 threads never straddle a wave: their exchanges need
+  // no block barrier, and waves of one block run their FFTs independently
+  constexpr bool WL = (64 % T) == 0;
+  using Sync = typename std::conditional<WL, WaveSync, BlockSync>::type;
   const int tid = threadIdx.x;
   if (tid >= TH) {
+    if (WL) return Rr(0);
     if (MODE == X_FUSED) {
       idle_fft_syncs<N, typename PP::P>();
       idle_fft_syncs<N, typename PP::P>();
@@ -148,7 +154,7 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
       }
       v[e] = val;
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, Sync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[tix(tt + T * e)] = v[e];
@@ -171,7 +177,7 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
         yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
       }
     }
-    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, Sync{});
     if (!PF) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -190,7 +196,7 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
       if (active) st<NT>(x + base + tt + T * e, cvt<Cx>(xn));
       v[e] = cadd(cmul(bb[e], xn), yy[e]);              // next t = B x + y
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, Sync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[tix(tt + T * e)] = v[e];
@@ -212,7 +218,7 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
       }
       v[e] = val;
     }
-    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, typename PP::P>::run(v, tt, row, tws, Sync{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) t[base + tt + T * e] = v[e];
@@ -235,7 +241,7 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
         yy[e] = active ? cvt<Cc>(ld<NT>(y + p)) : mk<Cc>(0.0, 0.0);
       }
     }
-    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, +1, 1, typename PP::P>::run(v, tt, row, tws, Sync{});
     if (!PF) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -314,7 +320,10 @@ __device__ __forceinline__ void spass_body(C* __restrict__ data, const C* __rest
   const long col = col0 + c;
   if (TILED) S = W;
   const long base = TILED ? col0 * N + c : b * N * S + col;
-  LdsCol<C, W> line{lds + c};
+  // the padded column's split of positions holds for this plan only
+  static_assert(!TILED || std::is_same<typename PP::P, Plan<16, 16, 4>>::value, "tiled column plan");
+  using Line = typename std::conditional<TILED, LdsColP<C, W>, LdsCol<C, W>>::type;
+  Line line{lds + c};
   C v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = data[base + (long)(tt + T * e) * S];
