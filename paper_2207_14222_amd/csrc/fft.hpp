@@ -243,6 +243,10 @@ struct WaveSync {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
 };
+// Exchange barrier for lines of T threads: wave-local when no line straddles
+// a wave (T divides 64), block-wide otherwise.
+template <int T> constexpr bool line_in_wave() { return (64 % T) == 0; }
+template <int T> using LineSync = typename std::conditional<line_in_wave<T>(), WaveSync, BlockSync>::type;
 
 // Reductions ----------------------------------------------------------------
 // R is float (norms of complex64 iterations) or double (FP64 residuals).

@@ -282,7 +282,9 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
   const long base = k * n + vbase;       // plane k
   LdsRow<Cc> row{rows + (k * LPB + li) * PADN};
   // the flux planes' values of this thread's voxels through LDS (plane 0
-  // takes part in the barriers only); the rows are free on entry and exit
+  // takes part in the barriers only); the rows are free on entry and exit.
+  // The FFTs of a line held by one wave synchronise that wave only: the
+  // block barriers of the exchange order every use of a row by other waves
   auto exch = [&](const Cc (&mine)[E], Cc (&fl)[D][E]) {
 #pragma unroll
     for (int e = 0; e < E; ++e) row[tt + T * e] = mine[e];
@@ -331,7 +333,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
     exch(xv, fl);
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = cadd(bapply(e, xv[e], fl), ld(y, e));
-    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, LineSync<T>{});
     if (act) {
 #pragma unroll
       for (int e = 0; e < E; ++e) spec[base + tt + T * e] = a[e];
@@ -346,7 +348,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
         x[base + tt + T * e] = cvt<Cx>(a[e]);
       }
     }
-    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, LineSync<T>{});
     if (act) {
 #pragma unroll
       for (int e = 0; e < E; ++e) spec[base + tt + T * e] = a[e];
@@ -360,7 +362,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
       xv[e] = ld(x, e);
       yv[e] = ld(y, e);
     }
-    FftRun<Cc, N, E, +1, 1, P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, +1, 1, P>::run(a, tt, row, tws, LineSync<T>{});
 #pragma unroll
     for (int e = 0; e < E; ++e) z[e] = csub(a[e], xv[e]);
     exch(z, fl);
@@ -378,7 +380,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
     exch(xv, fl);
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = cadd(bapply(e, xv[e], fl), yv[e]);
-    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, -1, 1, P>::run(a, tt, row, tws, LineSync<T>{});
     if (act) {
 #pragma unroll
       for (int e = 0; e < E; ++e) spec[base + tt + T * e] = a[e];
@@ -392,7 +394,7 @@ k_fx_row(Cc* __restrict__ spec, Cx* __restrict__ x, const Cx* __restrict__ y, co
       a[e] = act ? spec[base + tt + T * e] : mk<Cc>(0.0, 0.0);
       xv[e] = ld(x, e);
     }
-    FftRun<Cc, N, E, +1, 1, P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<Cc, N, E, +1, 1, P>::run(a, tt, row, tws, LineSync<T>{});
     exch(xv, fl);
     double rr = 0.0, yy = 0.0;
 #pragma unroll

@@ -105,7 +105,7 @@ k_kfirst(C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ B, co
   load_twiddles<C, N>(tws, tw);
   const int tid = threadIdx.x;
   if (tid >= TH) {
-    idle_fft_syncs<N, typename PP::P>();
+    if (!line_in_wave<T>()) idle_fft_syncs<N, typename PP::P>();
     return;
   }
   const int tt = tid % T, li = tid / T;
@@ -124,7 +124,7 @@ k_kfirst(C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ B, co
     }
     a[e] = val;
   }
-  FftRun<C, N, E, -1, 1, typename PP::P>::run(a, tt, row, tws, BlockSync{});
+  FftRun<C, N, E, -1, 1, typename PP::P>::run(a, tt, row, tws, LineSync<T>{});
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) t[base + tt + T * e] = a[e];
@@ -159,7 +159,7 @@ k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ 
     C a[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) a[e] = active ? t[base + tt + T * e] : mk<C>(0.0, 0.0);
-    FftRun<C, N, E, +1, 1, typename PP::P>::run(a, tt, row, tws, BlockSync{});
+    FftRun<C, N, E, +1, 1, typename PP::P>::run(a, tt, row, tws, LineSync<T>{});
     if (active) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
@@ -180,7 +180,7 @@ k_klast(const C* __restrict__ t, const C* __restrict__ v, const C* __restrict__ 
         if (dots & 8) vv2 += (double)vv.x * vv.x + (double)vv.y * vv.y;
       }
     }
-  } else {
+  } else if (!line_in_wave<T>()) {
     idle_fft_syncs<N, typename PP::P>();
   }
   if (dots & 1) block_partial2(qr, qi, scratch, rows, rows + pitch);
@@ -306,7 +306,7 @@ k_cgcg_first(C* __restrict__ t, C* __restrict__ x, C* __restrict__ r, C* __restr
   load_twiddles<C, N>(tws, tw);
   const int tid = threadIdx.x;
   if (tid >= TH) {
-    idle_fft_syncs<N, typename PP::P>();
+    if (!line_in_wave<T>()) idle_fft_syncs<N, typename PP::P>();
     return;
   }
   const C alpha = mk<C>(ar, ai);
@@ -332,7 +332,7 @@ k_cgcg_first(C* __restrict__ t, C* __restrict__ x, C* __restrict__ r, C* __restr
     }
     a[e] = val;
   }
-  FftRun<C, N, E, -1, 1, typename PP::P>::run(a, tt, row, tws, BlockSync{});
+  FftRun<C, N, E, -1, 1, typename PP::P>::run(a, tt, row, tws, LineSync<T>{});
   if (active) {
 #pragma unroll
     for (int e = 0; e < E; ++e) t[base + tt + T * e] = a[e];

@@ -118,8 +118,8 @@ __device__ __forceinline__ typename real_of<Cc>::type xpass_body(Cc* __restrict_
   constexpr int PADN = LdsRow<Cc>::padded(N);
   // lines of at most 64 threads never straddle a wave: their exchanges need
   // no block barrier, and waves of one block run their FFTs independently
-  constexpr bool WL = (64 % T) == 0;
-  using Sync = typename std::conditional<WL, WaveSync, BlockSync>::type;
+  constexpr bool WL = line_in_wave<T>();
+  using Sync = LineSync<T>;
   const int tid = threadIdx.x;
   if (tid >= TH) {
     if (WL) return Rr(0);
