@@ -264,37 +264,41 @@ k_conv27(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const f
   }
 }
 
-// 3x3x3 convolution, LDS-staged: a block computes a brick of 1 x BY x BX
-// output voxels (BX = 16 BXT, BY = 16 / BXT: 16 tiles of 16 voxels, 4 per
-// wave) and, for each 16-channel input plane in turn, stages the 3 x (BY+2) x
-// (BX+2) input voxels it touches (halo zero-filled at the grid faces) in LDS,
-// from where all 27 taps read their operands (16 bytes per lane, two taps per
-// v_mfma_f32_16x16x32 bf16).  Needs W % BX == 0 and H % BY == 0.
-template <int BXT> struct ConvTile {
+// 3x3x3 convolution, LDS-staged: a block computes a brick of ZB x BY x BX
+// output voxels (BX = 16 BXT, BY = 16 / BXT: 16 tiles of 16 voxels per
+// z-plane, 4 per wave, four waves per z-plane) and, for each 16-channel input
+// plane in turn, stages the (ZB+2) x (BY+2) x (BX+2) input voxels it touches
+// (halo zero-filled at the grid faces) in LDS, from where all 27 taps read
+// their operands (16 bytes per lane, two taps per v_mfma_f32_16x16x32 bf16).
+// Two z-planes per block stage 4 planes for 2 outputs instead of 3 for 1.
+// Needs W % BX == 0, H % BY == 0 and D % ZB == 0.
+template <int BXT, int ZB = 1> struct ConvTile {
   static constexpr int BX = 16 * BXT, BY = 16 / BXT, SX = BX + 2, SY = BY + 2;
-  static constexpr int PLANE_U4 = 3 * SY * SX * 2;   // two 16-byte halves per staged voxel
+  static constexpr int PLANE_U4 = (ZB + 2) * SY * SX * 2;   // two 16-byte halves per staged voxel
+  static constexpr int THREADS = 256 * ZB;
 };
 
-template <int CIN, int COUT, int SIGN, bool RELU, int BXT>
-__global__ void __launch_bounds__(256)
+template <int CIN, int COUT, int SIGN, bool RELU, int BXT, int ZB = 1>
+__global__ void __launch_bounds__(256 * ZB)
 k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const float* __restrict__ bias,
            uint16_t* __restrict__ out_bf, float* __restrict__ out_f32, int cstore, int D, int H, int W) {
-  using TL = ConvTile<BXT>;
-  constexpr int NT = COUT / 16, KC = CIN / 16;
+  using TL = ConvTile<BXT, ZB>;
+  constexpr int NT = COUT / 16, KC = CIN / 16, NTH = TL::THREADS;
   constexpr int BX = TL::BX, BY = TL::BY, SX = TL::SX, SY = TL::SY;
   __shared__ uint4 stg[TL::PLANE_U4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = (tid >> 6) & 3, zq = tid >> 8;
   const int i = lane & 15, g = lane >> 4;
   const long V = (long)D * H * W;
   const int nxb = W / BX, nyb = H / BY;
-  const int xb = blockIdx.x % nxb, yb = (blockIdx.x / nxb) % nyb, z = blockIdx.x / (nxb * nyb);
+  const int xb = blockIdx.x % nxb, yb = (blockIdx.x / nxb) % nyb, z0 = (blockIdx.x / (nxb * nyb)) * ZB;
   const int x0 = xb * BX, y0 = yb * BY;
-  // the wave's 4 tiles: tile q = 4 wave + m at row q / BXT, x offset 16 (q % BXT)
+  // the wave's 4 tiles in output plane z0 + zq: tile q = 4 wave + m at row
+  // q / BXT, x offset 16 (q % BXT)
   int lbase[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int q = 4 * wave + m, r = q / BXT, xt = q % BXT;
-    lbase[m] = (1 * SY + r + 1) * SX + 16 * xt + i + 1;
+    lbase[m] = ((zq + 1) * SY + r + 1) * SX + 16 * xt + i + 1;
   }
   v4f acc[4][NT];
 #pragma unroll
@@ -307,7 +311,7 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
     auto stage = [&](int u) -> uint4 {
       const int half = u & 1, vox = u >> 1;
       const int sx = vox % SX, sy = (vox / SX) % SY, sz = vox / (SX * SY);
-      const int zz = z - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
+      const int zz = z0 - 1 + sz, yy = y0 - 1 + sy, xx = x0 - 1 + sx;
       if (zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < W)
         return in4[((long)kc * V + ((long)zz * H + yy) * W + xx) * 2 + half];
       return uint4{0u, 0u, 0u, 0u};
@@ -317,20 +321,20 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
       // followed at once by its store would wait out each load's latency
       // (batches of 5 measured 2% slower; with more input planes the held
       // loads cost occupancy and the plain loop below was faster)
-      constexpr int NU = (TL::PLANE_U4 + 255) / 256;
+      constexpr int NU = (TL::PLANE_U4 + NTH - 1) / NTH;
       uint4 q[NU];
 #pragma unroll
       for (int k = 0; k < NU; ++k) {
-        const int u = tid + 256 * k;
+        const int u = tid + NTH * k;
         q[k] = u < TL::PLANE_U4 ? stage(u) : uint4{0u, 0u, 0u, 0u};
       }
 #pragma unroll
       for (int k = 0; k < NU; ++k) {
-        const int u = tid + 256 * k;
+        const int u = tid + NTH * k;
         if (u < TL::PLANE_U4) stg[u] = q[k];
       }
     } else {
-      for (int u = tid; u < TL::PLANE_U4; u += 256) stg[u] = stage(u);
+      for (int u = tid; u < TL::PLANE_U4; u += NTH) stg[u] = stage(u);
     }
     __syncthreads();
     for (int tp = 0; tp < 14; ++tp) {
@@ -356,7 +360,7 @@ k_conv_lds(const uint16_t* __restrict__ in, const uint4* __restrict__ wpk, const
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int q = 4 * wave + m, r = q / BXT, xt = q % BXT;
-      const long v0 = ((long)z * H + y0 + r) * W + x0 + 16 * xt;
+      const long v0 = ((long)(z0 + zq) * H + y0 + r) * W + x0 + 16 * xt;
       conv_store<RELU>(acc[m][t], t, v0, lane, bb, V, out_bf, out_f32, cstore);
     }
   }

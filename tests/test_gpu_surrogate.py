@@ -193,6 +193,47 @@ def test_conv_wide_schedule(cin, cout, grid):
     assert np.linalg.norm(dw.cpu().double().numpy() - ref) / np.linalg.norm(ref) < 1e-4
 
 
+@pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (16, 48)])
+def test_conv_two_plane_bricks(cin, cout):
+    """128^3 (2^21 voxels; convolutions of 16 input channels run on bricks of
+    two output z-planes, 512 threads): forward and input gradient against
+    direct float64 sums on sampled voxels, both planes of a brick, brick edges
+    and the grid faces included."""
+    _need_gpu()
+    L = _lib()
+    D = H = W = 128
+    V = D * H * W
+    grid = (D, H, W)
+    print(f"[gpu-case] conv two-plane bricks {cin}->{cout} grid {grid}", flush=True)
+    g = torch.Generator().manual_seed(11 + cin + cout)
+    xc = bf(torch.randn(cin, D, H, W, generator=g))
+    x = from_cf(xc).cuda()
+    w = bf(torch.randn(cout, 27, cin, generator=g) / math.sqrt(cin * 27)).cuda()
+    b = torch.randn(cout, generator=g).cuda()
+    out = torch.empty(V, cout, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d(_p(x), _p(pack(L, w, False)), _p(b), _p(out), 1, cout, D, H, W, cin, cout, 27, 1, 0,
+                                 _st()) == 0
+    gyc = bf(torch.randn(cout, D, H, W, generator=g))
+    gy = from_cf(gyc).cuda()
+    gx = torch.empty(V, cin, dtype=torch.float32, device="cuda")
+    assert L.lib().usp_nn_conv3d(_p(gy), _p(pack(L, w, True)), None, _p(gx), 1, cin, D, H, W, cout, cin, 27, -1, 0,
+                                 _st()) == 0
+    xn, gyn = xc.double().numpy(), gyc.double().numpy()
+    wn = w.float().cpu().double().numpy()
+    bn = b.cpu().double().numpy()
+    outn = out.cpu().double().numpy().reshape(D, H, W, cout)
+    gxn = gx.cpu().double().numpy().reshape(D, H, W, cin)
+    rng = np.random.default_rng(1)
+    pts = [tuple(int(rng.integers(0, n)) for n in grid) for _ in range(64)]
+    pts += [(0, 0, 0), (1, 0, 0), (D - 1, H - 1, W - 1), (D - 2, H - 1, W - 1), (0, H - 1, 0), (1, 3, 63),
+            (2, 4, 64), (3, 7, 127), (64, 63, 64), (65, 64, 63), (127, 0, 65), (126, 127, 1)]
+    for (z, y, x_) in pts:
+        r = conv_at(xn, wn, bn, z, y, x_, 1)
+        assert np.linalg.norm(outn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
+        r = conv_at(gyn, wn.transpose(2, 1, 0), None, z, y, x_, -1)
+        assert np.linalg.norm(gxn[z, y, x_] - r) / np.linalg.norm(r) < 1e-5, (z, y, x_)
+
+
 @pytest.mark.parametrize("grid", [(1, 1, 32), (2, 3, 96), (5, 2, 64), (3, 9, 32)])
 @pytest.mark.parametrize("cin,cout", [(16, 16), (48, 16), (192, 64)])
 def test_weight_gradient_sweep_edge_grids(cin, cout, grid):
