@@ -48,25 +48,26 @@ TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profile
 
 
 def recorded_traffic(plan, shape):
-    """HBM bytes per x_fused launch from the committed rocprofv3 counter summary,
-    or None if the kernel sources or the plan differ from those it was taken with."""
+    """HBM bytes per x_fused launch from the committed rocprofv3 counter summary
+    (one entry per load plan of the fused pass), or None if the kernel sources
+    changed since the counters were taken or the plan has no entry."""
     import hashlib
     if shape != (256, 256, 256) or not os.path.exists(TRAFFIC_FILE):
         return None
-    kv = {}
+    sha, per_plan = None, {}
     for line in open(TRAFFIC_FILE):
         line = line.strip()
-        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "plan", "sources_sha256_16"):
-            k, v = line.split(":", 1)
-            kv[k] = v.strip()
+        if line.startswith("sources_sha256_16:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic x_prefetch="):
+            key, v = line.split(":", 1)
+            f = dict(t.split("=") for t in key.split()[1:])
+            per_plan[(int(f["x_prefetch"]), int(f["x_stream"]))] = int(v)
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2207_14222_amd", "csrc")
     src = open(os.path.join(csrc, "fft.hpp"), "rb").read() + open(os.path.join(csrc, "passes.hpp"), "rb").read()
-    if hashlib.sha256(src).hexdigest()[:16] != kv.get("sources_sha256_16"):
+    if hashlib.sha256(src).hexdigest()[:16] != sha:
         return None
-    rp = [int(v) for v in kv.get("plan", "").split(",")]
-    if len(rp) != 4 or (rp[0], rp[3]) != (plan["x_prefetch"], plan["x_stream"]):
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    return per_plan.get((plan["x_prefetch"], plan["x_stream"]))
 
 
 def log(msg):
