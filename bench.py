@@ -173,7 +173,7 @@ def bench_batch(args, log, sequential=True):
     (plain complex128 checked every 20, and refined complex64)."""
     import torch
     from paper_2207_14222_amd import media, solver
-    sizes = media.batch_sizes(args.batch_n, seed=4)
+    sizes = [args.batch_side] * args.batch_n if args.batch_side else media.batch_sizes(args.batch_n, seed=4)
     cans, ops = [], []
     for i, n in enumerate(sizes):
         p = media.helmholtz_disks(n=n, seed=4000 + i)
@@ -181,7 +181,7 @@ def bench_batch(args, log, sequential=True):
         ops.append(solver.Operator(cans[-1].symbol, cans[-1].B, refine=True))
     log(f"batch: {len(sizes)} problems prepared")
     xs = [torch.zeros_like(c.y) for c in cans]
-    b = solver.Batch(ops, [c.y for c in cans], xs, alpha=args.batch_alpha, tol=args.tol, maxit=20000)
+    b = solver.Batch(ops, [c.y for c in cans], xs, alpha=args.batch_alpha, tol=args.tol, maxit=args.batch_maxit)
     if args.batch_variant is None:
         variant = b.autotune(refine_every=args.batch_refine_every)
     else:
@@ -528,6 +528,11 @@ def main():
     ap.add_argument("--batch-only", action="store_true",
                     help="profiling aid: run only the batched workload's autotuned solve (no headline line)")
     ap.add_argument("--batch-n", type=int, default=96)
+    ap.add_argument("--batch-side", type=int, default=0,
+                    help="profiling aid: every batched problem of this side instead of the drawn sizes")
+    ap.add_argument("--batch-maxit", type=int, default=20000,
+                    help="profiling aid: iteration cap of the batched solve (a cap below the iterations to "
+                         "tolerance keeps every problem in every launch)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-initial-guess workload")
     ap.add_argument("--no-flux", action="store_true", help="skip the flux-form tensor diffusion workload")
     ap.add_argument("--no-eigen", action="store_true", help="skip the eigenmode workload")
